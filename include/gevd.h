@@ -1,0 +1,170 @@
+/*
+ * gevd.h -- C interface of the MI355X (gfx950) dense generalized
+ * Hermitian eigensolver  H C = eps S C.
+ *
+ * The problem is the paper's Eq. (2): H and S are the Hamiltonian and
+ * overlap matrices of a non-orthogonal basis, S is Hermitian positive
+ * definite, C holds eigenvectors as columns and eps the eigenvalues.  The
+ * solve follows the paper's section "Solving the generalized eigenproblem":
+ * Cholesky S = U^H U (step 1), inversion U -> U^{-1} (step 2), the two
+ * products A = U^{-H} H U^{-1} (step 3), the standard eigenproblem of A, and
+ * the back-transformation C = U^{-1} C~.  The standard eigenproblem uses the
+ * two-stage route (full -> band -> tridiagonal) that the paper names for
+ * subsets of eigenvectors (section "ELPA - Usability"), a divide-and-conquer
+ * tridiagonal solver, and back-transformation of only the wanted vectors.
+ * Per-step entry points exist because the paper's library offers an
+ * interface for each transformation step (section "ELPA").
+ *
+ * Conventions for every call below
+ *  - Matrices are column-major: element (i, j) at p[i + j*ld], ld >= n.
+ *  - Real problems use double; complex problems use interleaved
+ *    (re, im) doubles, layout-compatible with C99 double _Complex.
+ *  - Matrix and vector pointers are DEVICE pointers on the handle's device,
+ *    owned by the caller; the library never frees them.
+ *  - Work is enqueued on the handle's stream.  Calls that return an info
+ *    value computed on the device (positive definiteness) synchronise that
+ *    stream before returning; the others return after enqueueing.
+ *  - Workspace is owned by the handle: allocated on first use, grown when a
+ *    larger problem arrives, released by gevd_destroy.
+ *  - Return value: 0 on success; -i when argument i (1-based) is invalid
+ *    (checked on the host before any launch); j > 0 when S is not positive
+ *    definite at leading minor j (paper: S must not be numerically
+ *    singular); or one of the GEVD_E_* codes.
+ */
+#ifndef GEVD_H
+#define GEVD_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GEVD_OK 0
+#define GEVD_E_NONFINITE (-1001) /* NaN or Inf found in H or S */
+#define GEVD_E_NOCONV (-1002)    /* tridiagonal solver failed to converge */
+#define GEVD_E_NOMEM (-1003)     /* device memory exhausted */
+#define GEVD_E_HIP (-1004)       /* a HIP runtime call failed */
+#define GEVD_E_STATE (-1005)     /* call order violated (e.g. no overlap set) */
+#define GEVD_E_HANG (-1006)      /* a device-side wait exceeded its bound */
+
+/* Scalar type of a problem. */
+#define GEVD_REAL 0    /* real symmetric, double */
+#define GEVD_COMPLEX 1 /* complex Hermitian, interleaved double pairs */
+
+/* Options for gevd_set_option. */
+#define GEVD_OPT_BAND 1     /* half-bandwidth b of the intermediate band (0 = auto) */
+#define GEVD_OPT_TIMING 2   /* 1: record per-phase device times (events) */
+#define GEVD_OPT_LEAF 3     /* divide-and-conquer leaf size (0 = auto) */
+
+/* Phases reported by gevd_get_timings (milliseconds, last solve). */
+#define GEVD_PH_CHOLESKY 0  /* S = U^H U */
+#define GEVD_PH_INVERT 1    /* U -> U^{-1} */
+#define GEVD_PH_MULTIPLY 2  /* A = U^{-H} H U^{-1} */
+#define GEVD_PH_BAND 3      /* full -> band */
+#define GEVD_PH_TRIDIAG 4   /* band -> tridiagonal */
+#define GEVD_PH_SOLVE 5     /* tridiagonal divide-and-conquer */
+#define GEVD_PH_BACK2 6     /* back-transform through band -> tridiagonal */
+#define GEVD_PH_BACK1 7     /* back-transform through full -> band */
+#define GEVD_PH_MULT 8      /* C = U^{-1} C~ */
+#define GEVD_NPHASE 9
+
+typedef struct gevd_ctx *gevd_handle;
+
+/* Create a handle bound to HIP device `device`, using the default stream.
+ * *h receives the handle.  Errors: -1 (h NULL), GEVD_E_HIP. */
+int gevd_create(gevd_handle *h, int device);
+
+/* Release the handle and all workspace it owns (synchronises its stream). */
+int gevd_destroy(gevd_handle h);
+
+/* Use `stream` (a hipStream_t, e.g. torch.cuda.current_stream().cuda_stream)
+ * for all following work of this handle. */
+int gevd_set_stream(gevd_handle h, void *stream);
+
+/* Set an integer option (GEVD_OPT_*).  Band width must be 0 or in [8, 64]. */
+int gevd_set_option(gevd_handle h, int option, int value);
+
+/* Human-readable text for a return code (static storage). */
+const char *gevd_strerror(int code);
+
+/* Bytes of device workspace the handle holds for a (dtype, n, nev) solve;
+ * a caller admitting work by memory footprint adds its own n x n H, S and
+ * n x nev C.  Host-only computation. */
+size_t gevd_workspace_bytes(int dtype, int n, int nev);
+
+/* Whole generalized solve (paper Eq. (2) by its three reduction steps and
+ * the back-transformation).
+ *  dtype     GEVD_REAL or GEVD_COMPLEX
+ *  n         order of H and S (>= 1)
+ *  nev       number of wanted eigenpairs, the nev algebraically smallest
+ *            (1 <= nev <= n)
+ *  H, ldh    upper triangle read (the strictly lower part is ignored);
+ *            overwritten (used as workspace)
+ *  S, lds    upper triangle read; on return its upper triangle holds U with
+ *            S = U^H U; the strictly lower part is clobbered
+ *  eval      n doubles: all eigenvalues in ascending order
+ *  C, ldc    n x nev: eigenvectors of the nev smallest eigenvalues, with
+ *            C^H S C = I
+ * Synchronises the stream.  Returns 0, -i, j > 0 (S not positive definite
+ * at minor j; nothing else is computed), or GEVD_E_*. */
+int gevd_solve(gevd_handle h, int dtype, int n, int nev, void *H, int ldh, void *S, int lds,
+               double *eval, void *C, int ldc);
+
+/* Step 1: Cholesky factorisation S = U^H U in place (upper triangle read
+ * and overwritten with U; the strictly lower triangle is clobbered).
+ * Synchronises the stream; returns 0 or j > 0 for a non positive definite
+ * leading minor j. */
+int gevd_cholesky(gevd_handle h, int dtype, int n, void *S, int lds);
+
+/* Step 2: Uinv = U^{-1} for the upper triangular U (upper triangle of U
+ * read).  Uinv receives the full n x n matrix with exact zeros below the
+ * diagonal.  U and Uinv must not overlap. */
+int gevd_invert_upper(gevd_handle h, int dtype, int n, const void *U, int ldu, void *Uinv, int ldi);
+
+/* Step 3: A = Uinv^H H Uinv (the paper's two products), H read from its
+ * upper triangle (the strictly lower part of H is overwritten by the
+ * Hermitian mirror), Uinv upper triangular (lower part ignored).  A
+ * receives the full Hermitian matrix.  A must not overlap H or Uinv. */
+int gevd_reduce(gevd_handle h, int dtype, int n, void *H, int ldh, const void *Uinv, int ldi, void *A,
+                int lda);
+
+/* Standard Hermitian eigenproblem A z = eps z by full -> band ->
+ * tridiagonal -> divide-and-conquer -> back-transformation.
+ *  A, lda   full Hermitian matrix (both triangles read); clobbered
+ *  eval     n doubles, all eigenvalues ascending
+ *  Z, ldz   n x nev orthonormal eigenvectors of the nev smallest */
+int gevd_eigh(gevd_handle h, int dtype, int n, int nev, void *A, int lda, double *eval, void *Z, int ldz);
+
+/* Back-transformation C = Uinv Ct (n x nev), Uinv upper triangular. */
+int gevd_backtransform(gevd_handle h, int dtype, int n, int nev, const void *Uinv, int ldi, const void *Ct,
+                       int ldct, void *C, int ldc);
+
+/* First stage only: full Hermitian A (clobbered) -> band of half-bandwidth
+ * b (the handle's band option, see gevd_get_band).  The band is returned
+ * in lower band storage: Bd[(i - j) + j*ldb] = B[i, j] for 0 <= i-j <= b,
+ * ldb >= b + 1. */
+int gevd_band(gevd_handle h, int dtype, int n, void *A, int lda, void *Bd, int ldb);
+
+/* Half-bandwidth the handle uses for order n and dtype. */
+int gevd_get_band(gevd_handle h, int dtype, int n);
+
+/* Both reduction stages: full Hermitian A (clobbered) -> real symmetric
+ * tridiagonal (d: n diagonal, e: n-1 subdiagonal), device doubles. */
+int gevd_tridiagonalize(gevd_handle h, int dtype, int n, void *A, int lda, double *d, double *e);
+
+/* Real symmetric tridiagonal eigenproblem by divide-and-conquer.
+ *  d, e     device doubles (n, n-1); not modified
+ *  eval     n eigenvalues ascending
+ *  Z, ldz   n x nev real orthonormal eigenvectors of the nev smallest */
+int gevd_stedc(gevd_handle h, int n, int nev, const double *d, const double *e, double *eval, double *Z,
+               int ldz);
+
+/* Per-phase device times (ms) of the last gevd_solve or gevd_eigh when
+ * GEVD_OPT_TIMING is on; ms must hold nphase doubles.  Synchronises. */
+int gevd_get_timings(gevd_handle h, double *ms, int nphase);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GEVD_H */

@@ -1,0 +1,167 @@
+// Orchestration of the standard Hermitian eigenproblem A z = eps z:
+// full -> band (he2hb) -> tridiagonal (hb2st) -> divide-and-conquer (stedc)
+// -> back-transformation through the bulge-chasing reflectors and then
+// through the panel reflectors, for the wanted columns only.
+#include <algorithm>
+
+#include "stages.hpp"
+
+namespace gevd {
+namespace {
+
+struct Carve {
+    char* p;
+    size_t off = 0;
+    template <typename U>
+    U* take(size_t elems) {
+        off = (off + 255) & ~size_t(255);
+        U* r = reinterpret_cast<U*>(p ? p + off : nullptr);
+        off += elems * sizeof(U);
+        return r;
+    }
+};
+
+int count_panels(int n, int b) {
+    int np = 0;
+    while (n - np * b - b >= 2) ++np;
+    return np;
+}
+
+constexpr int SKB = 4;  // split of the long inner dimension in the stage-1 back-transform
+
+template <typename T>
+struct EighWs {
+    BandRefl<T> R1;
+    ChaseRefl<T> R2;
+    T* Bw;
+    long ldw;
+    double *d, *e;
+    int* sync_area;
+    T* he_work;      // he2hb scratch
+    T* bb_work;      // back_band scratch
+    double* Zr;      // real eigenvectors from D&C (n x nev)
+    char* dc_ws;     // D&C scratch
+};
+
+template <typename T>
+size_t carve_eigh(char* base, int n, int nev, int b, int leaf, EighWs<T>* out) {
+    Carve c{base};
+    EighWs<T> w;
+    const int np = count_panels(n, b);
+    w.R1.n = n;
+    w.R1.b = b;
+    w.R1.np = np;
+    w.R1.V = c.take<T>(np > 0 ? w.R1.voff(np) : 1);
+    w.R1.Tf = c.take<T>((size_t)std::max(np, 1) * b * b);
+    w.ldw = 2 * b + 1;
+    w.Bw = c.take<T>((size_t)w.ldw * n);
+    const int nsw = n - 1;
+    const int tmax = n > 1 ? (n - 1 + b - 1) / b : 0;
+    w.R2.n = n;
+    w.R2.b = b;
+    w.R2.nsw = nsw;
+    w.R2.tmax = tmax;
+    w.R2.V2 = c.take<T>((size_t)std::max(tmax, 1) * std::max(nsw, 1) * b);
+    w.R2.tau2 = c.take<T>((size_t)std::max(tmax, 1) * std::max(nsw, 1));
+    w.d = c.take<double>(n);
+    w.e = c.take<double>(n);
+    w.sync_area = c.take<int>((size_t)n + 8);
+    w.he_work = c.take<T>(he2hb_ws_elems<T>(n, b));
+    w.bb_work = c.take<T>(back_band_ws_elems<T>(n, nev, b));
+    w.Zr = c.take<double>((size_t)n * nev);
+    w.dc_ws = c.take<char>(stedc_ws_bytes(n, nev, leaf));
+    if (out) *out = w;
+    return c.off;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- stage 1 back
+// Z <- Q1 Z with Q1 = prod_p (I - V_p T_p V_p^H): panels last-first, each as
+// X = V^H Z_rows (split inner dimension), Y = T X, Z_rows -= V Y.
+template <typename T>
+size_t back_band_ws_elems(int n, int nev, int b) {
+    return (size_t)(2 + SKB) * b * nev + 64;
+}
+
+template <typename T>
+int back_band(const StageCtx& c, const BandRefl<T>& R, int nev, T* Z, long ldz, T* work) {
+    const int b = R.b, n = R.n;
+    T* X = work;
+    T* Y = work + (size_t)b * nev;
+    T* sk = work + (size_t)2 * b * nev;
+    const T one = from_real<T>(1.0), mone = from_real<T>(-1.0), zero = zero_of<T>();
+    for (int p = R.np - 1; p >= 0; --p) {
+        const int c0 = p * b, m = n - c0 - b;
+        const T* V = R.V + R.voff(p);
+        const T* Tf = R.Tf + (size_t)p * b * b;
+        T* Zr = Z + (c0 + b);
+        int rc = gemm<T>(c.st, OP_C, OP_N, b, nev, m, one, V, m, Zr, ldz, zero, X, b, K_FULL, T_ALL, Batch(),
+                         m >= 1024 ? SKB : 1, sk);
+        if (rc) return rc;
+        if ((rc = gemm<T>(c.st, OP_N, OP_N, b, nev, b, one, Tf, b, X, b, zero, Y, b, K_A_UPPER))) return rc;
+        if ((rc = gemm<T>(c.st, OP_N, OP_N, m, nev, b, mone, V, m, Y, b, one, Zr, ldz))) return rc;
+    }
+    return 0;
+}
+
+template <typename T>
+size_t band_ws_bytes(int n, int b) {
+    return carve_eigh<T>(nullptr, n, 1, b, 0, nullptr) + 256;
+}
+
+template <typename T>
+size_t eigh_ws_bytes(int n, int nev, int b, int leaf) {
+    return carve_eigh<T>(nullptr, n, nev, b, leaf, nullptr) + 256;
+}
+
+template <typename T>
+int band_run(const StageCtx& c, int n, T* A, long lda, T* Bd, long ldb, char* ws) {
+    EighWs<T> w;
+    carve_eigh<T>(ws, n, 1, c.b, 0, &w);
+    // he2hb writes all ldb rows; rows beyond b are zero
+    return he2hb<T>(c, n, A, lda, w.R1, Bd, ldb, w.he_work);
+}
+
+template <typename T>
+int tridiag_run(const StageCtx& c, int n, T* A, long lda, double* d, double* e, char* ws) {
+    EighWs<T> w;
+    carve_eigh<T>(ws, n, 1, c.b, c.leaf, &w);
+    int rc = he2hb<T>(c, n, A, lda, w.R1, w.Bw, w.ldw, w.he_work);
+    if (rc) return rc;
+    double* ee = e ? e : w.e;
+    return hb2st<T>(c, n, w.Bw, w.ldw, w.R2, d, ee, w.sync_area);
+}
+
+template <typename T>
+int eigh_run(const StageCtx& c, int n, int nev, T* A, long lda, double* eval, T* Z, long ldz, char* ws) {
+    EighWs<T> w;
+    carve_eigh<T>(ws, n, nev, c.b, c.leaf, &w);
+    int rc = he2hb<T>(c, n, A, lda, w.R1, w.Bw, w.ldw, w.he_work);
+    if (rc) return rc;
+    c.phase(GEVD_PH_TRIDIAG);
+    if ((rc = hb2st<T>(c, n, w.Bw, w.ldw, w.R2, w.d, w.e, w.sync_area))) return rc;
+    c.phase(GEVD_PH_SOLVE);
+    if ((rc = stedc_run(c, n, nev, w.d, w.e, eval, w.Zr, n, w.dc_ws))) return rc;
+    c.phase(GEVD_PH_BACK2);
+    if (is_cplx<T>::value) rc = real_to_scalar_z(c.st, n, nev, w.Zr, n, reinterpret_cast<zdouble*>(Z), ldz);
+    else rc = real_to_scalar_d(c.st, n, nev, w.Zr, n, reinterpret_cast<double*>(Z), ldz);
+    if (rc) return rc;
+    if ((rc = back_chase<T>(c, w.R2, nev, Z, ldz))) return rc;
+    c.phase(GEVD_PH_BACK1);
+    return back_band<T>(c, w.R1, nev, Z, ldz, w.bb_work);
+}
+
+#define INST(T)                                                                              \
+    template size_t back_band_ws_elems<T>(int, int, int);                                    \
+    template int back_band<T>(const StageCtx&, const BandRefl<T>&, int, T*, long, T*);       \
+    template size_t band_ws_bytes<T>(int, int);                                              \
+    template size_t eigh_ws_bytes<T>(int, int, int, int);                                    \
+    template int band_run<T>(const StageCtx&, int, T*, long, T*, long, char*);               \
+    template int tridiag_run<T>(const StageCtx&, int, T*, long, double*, double*, char*);    \
+    template int eigh_run<T>(const StageCtx&, int, int, T*, long, double*, T*, long, char*);
+INST(double)
+INST(zdouble)
+#undef INST
+
+}  // namespace gevd

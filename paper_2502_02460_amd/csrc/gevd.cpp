@@ -1,0 +1,497 @@
+// Host pipeline and C interface of the generalized eigensolver (gevd.h).
+//
+// Each entry point validates its arguments on the host, sizes the handle's
+// workspace, and enqueues kernels on the handle's stream.  The only host
+// waits are where a device-computed status must be returned (positive
+// definiteness, convergence) and at the end of a whole solve.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+
+#include "kernels.hpp"
+#include "stages.hpp"
+
+using namespace gevd;
+
+struct gevd_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int band_opt = 0;
+    int leaf_opt = 0;
+    int timing = 0;
+    char* ws = nullptr;  // workspace (device)
+    size_t ws_bytes = 0;
+    int* flags = nullptr;  // small device status area
+    hipEvent_t ev[GEVD_NPHASE + 1] = {};
+    bool ev_made = false;
+    bool ev_valid = false;
+};
+
+namespace {
+
+constexpr int NFLAGS = 16;
+enum { F_INFO = 0, F_NONFINITE = 1, F_NOCONV = 2, F_HANG = 3 };
+
+struct Bump {
+    char* base;
+    size_t off = 0;
+    explicit Bump(char* b) : base(b) {}
+    template <typename T>
+    T* take(size_t elems) {
+        off = (off + 255) & ~size_t(255);
+        T* p = reinterpret_cast<T*>(base ? base + off : nullptr);
+        off += elems * sizeof(T);
+        return p;
+    }
+};
+
+int ensure_ws(gevd_ctx* h, size_t bytes) {
+    if (bytes <= h->ws_bytes) return 0;
+    GEVD_HIP(hipSetDevice(h->device));
+    if (h->ws) {
+        GEVD_HIP(hipStreamSynchronize(h->stream));
+        GEVD_HIP(hipFree(h->ws));
+        h->ws = nullptr;
+        h->ws_bytes = 0;
+    }
+    size_t want = bytes + (bytes >> 4);
+    if (hipMalloc(&h->ws, want) != hipSuccess) {
+        (void)hipGetLastError();
+        h->ws = nullptr;
+        return GEVD_E_NOMEM;
+    }
+    h->ws_bytes = want;
+    return 0;
+}
+
+int read_flags(gevd_ctx* h, int* host) {
+    GEVD_HIP(hipMemcpyAsync(host, h->flags, NFLAGS * sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    GEVD_HIP(hipStreamSynchronize(h->stream));
+    return 0;
+}
+
+int clear_flags(gevd_ctx* h) {
+    GEVD_HIP(hipMemsetAsync(h->flags, 0, NFLAGS * sizeof(int), h->stream));
+    return 0;
+}
+
+void mark(gevd_ctx* h, int phase) {
+    if (h->timing && h->ev_made) (void)hipEventRecord(h->ev[phase], h->stream);
+}
+
+int pick_band(const gevd_ctx* h, int n) {
+    int b = h->band_opt > 0 ? h->band_opt : 32;
+    if (n <= 2 * b) b = std::max(1, std::min(b, n / 2));
+    return std::max(1, b);
+}
+
+// ------------------------------------------------------------- workspace plans
+template <typename T>
+size_t plan_cholesky(int n) {
+    Bump b(nullptr);
+    b.take<T>(potrf_work_elems<T>(n));
+    return b.off;
+}
+
+template <typename T>
+size_t plan_invert(int n) {
+    Bump b(nullptr);
+    b.take<T>(trtri_work_elems<T>(n));
+    return b.off;
+}
+
+template <typename T>
+size_t plan_reduce(int n) {
+    Bump b(nullptr);
+    b.take<T>((size_t)n * n);
+    return b.off;
+}
+
+// ------------------------------------------------------------- steps
+template <typename T>
+int do_cholesky(gevd_ctx* h, int n, T* S, int lds, char* ws) {
+    Bump b(ws);
+    T* work = b.take<T>(potrf_work_elems<T>(n));
+    return potrf<T>(h->stream, n, S, lds, work, h->flags + F_INFO);
+}
+
+template <typename T>
+int do_invert(gevd_ctx* h, int n, const T* U, int ldu, T* Uinv, int ldi, char* ws) {
+    Bump b(ws);
+    T* work = b.take<T>(trtri_work_elems<T>(n));
+    return trtri<T>(h->stream, n, U, ldu, Uinv, ldi, work);
+}
+
+// A = Uinv^H H Uinv: W = H Uinv (Uinv upper: inner range clipped per tile),
+// then the upper tiles of Uinv^H W, then the Hermitian mirror.
+template <typename T>
+int do_reduce(gevd_ctx* h, int n, T* H, int ldh, const T* Uinv, int ldi, T* A, int lda, char* ws) {
+    Bump b(ws);
+    T* W = b.take<T>((size_t)n * n);
+    const T one = from_real<T>(1.0), zero = zero_of<T>();
+    int rc = fill_lower_from_upper<T>(h->stream, n, H, ldh);
+    if (rc) return rc;
+    rc = gemm<T>(h->stream, OP_N, OP_N, n, n, n, one, H, ldh, Uinv, ldi, zero, W, n, K_B_UPPER);
+    if (rc) return rc;
+    rc = gemm<T>(h->stream, OP_C, OP_N, n, n, n, one, Uinv, ldi, W, n, zero, A, lda, K_A_LOWER, T_UPPER_TILES);
+    if (rc) return rc;
+    return fill_lower_from_upper<T>(h->stream, n, A, lda);
+}
+
+template <typename T>
+int do_backtransform(gevd_ctx* h, int n, int nev, const T* Uinv, int ldi, const T* Ct, int ldct, T* C, int ldc) {
+    const T one = from_real<T>(1.0), zero = zero_of<T>();
+    return gemm<T>(h->stream, OP_N, OP_N, n, nev, n, one, Uinv, ldi, Ct, ldct, zero, C, ldc, K_A_UPPER);
+}
+
+template <typename T>
+size_t plan_solve(const gevd_ctx* h, int n, int nev) {
+    Bump b(nullptr);
+    b.take<T>((size_t)n * n);  // Uinv
+    size_t rest = std::max({plan_cholesky<T>(n), plan_invert<T>(n), plan_reduce<T>(n),
+                            eigh_ws_bytes<T>(n, nev, pick_band(h, n), h->leaf_opt)});
+    return b.off + 256 + rest + (size_t)n * nev * sizeof(T) + 256;
+}
+
+template <typename T>
+int do_eigh(gevd_ctx* h, int n, int nev, T* A, int lda, double* eval, T* Z, int ldz, char* ws, bool timed) {
+    StageCtx sc{h->stream, h->flags + F_NOCONV, h->flags + F_HANG, pick_band(h, n), h->leaf_opt};
+    if (timed) {
+        sc.mark = [](void* p, int ph) { mark((gevd_ctx*)p, ph); };
+        sc.mark_arg = h;
+    }
+    return eigh_run<T>(sc, n, nev, A, lda, eval, Z, ldz, ws);
+}
+
+template <typename T>
+int do_solve(gevd_ctx* h, int n, int nev, T* H, int ldh, T* S, int lds, double* eval, T* C, int ldc) {
+    int rc = ensure_ws(h, plan_solve<T>(h, n, nev));
+    if (rc) return rc;
+    Bump b(h->ws);
+    T* Uinv = b.take<T>((size_t)n * n);
+    T* Ct = b.take<T>((size_t)n * nev);
+    char* rest = reinterpret_cast<char*>(b.take<char>(0));
+    if ((rc = clear_flags(h))) return rc;
+    if ((rc = check_finite_upper<T>(h->stream, n, H, ldh, h->flags + F_NONFINITE))) return rc;
+    if ((rc = check_finite_upper<T>(h->stream, n, S, lds, h->flags + F_NONFINITE))) return rc;
+    h->ev_valid = false;
+    mark(h, GEVD_PH_CHOLESKY);
+    if ((rc = do_cholesky<T>(h, n, S, lds, rest))) return rc;
+    int fl[NFLAGS];
+    if ((rc = read_flags(h, fl))) return rc;
+    if (fl[F_NONFINITE]) return GEVD_E_NONFINITE;
+    if (fl[F_INFO]) return fl[F_INFO];
+    mark(h, GEVD_PH_INVERT);
+    if ((rc = do_invert<T>(h, n, S, lds, Uinv, n, rest))) return rc;
+    mark(h, GEVD_PH_MULTIPLY);
+    if ((rc = do_reduce<T>(h, n, H, ldh, Uinv, n, H, ldh, rest))) return rc;
+    mark(h, GEVD_PH_BAND);
+    if ((rc = do_eigh<T>(h, n, nev, H, ldh, eval, Ct, n, rest, true))) return rc;
+    mark(h, GEVD_PH_MULT);
+    if ((rc = do_backtransform<T>(h, n, nev, Uinv, n, Ct, n, C, ldc))) return rc;
+    mark(h, GEVD_NPHASE);
+    if ((rc = read_flags(h, fl))) return rc;
+    if (fl[F_HANG]) return GEVD_E_HANG;
+    if (fl[F_NOCONV]) return GEVD_E_NOCONV;
+    h->ev_valid = h->timing != 0;
+    return 0;
+}
+
+bool bad_dtype(int t) { return t != GEVD_REAL && t != GEVD_COMPLEX; }
+
+}  // namespace
+
+// ============================================================== C interface
+extern "C" {
+
+int gevd_create(gevd_handle* out, int device) {
+    if (!out) return -1;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return -2;
+    gevd_ctx* h = new (std::nothrow) gevd_ctx();
+    if (!h) return GEVD_E_NOMEM;
+    h->device = device;
+    if (hipSetDevice(device) != hipSuccess || hipMalloc(&h->flags, NFLAGS * sizeof(int)) != hipSuccess) {
+        delete h;
+        return GEVD_E_HIP;
+    }
+    (void)hipMemset(h->flags, 0, NFLAGS * sizeof(int));
+    *out = h;
+    return 0;
+}
+
+int gevd_destroy(gevd_handle h) {
+    if (!h) return -1;
+    (void)hipSetDevice(h->device);
+    (void)hipStreamSynchronize(h->stream);
+    if (h->ws) (void)hipFree(h->ws);
+    if (h->flags) (void)hipFree(h->flags);
+    if (h->ev_made)
+        for (auto& e : h->ev) (void)hipEventDestroy(e);
+    delete h;
+    return 0;
+}
+
+int gevd_set_stream(gevd_handle h, void* stream) {
+    if (!h) return -1;
+    h->stream = reinterpret_cast<hipStream_t>(stream);
+    return 0;
+}
+
+int gevd_set_option(gevd_handle h, int option, int value) {
+    if (!h) return -1;
+    switch (option) {
+        case GEVD_OPT_BAND:
+            if (value != 0 && (value < 8 || value > 64)) return -3;
+            h->band_opt = value;
+            return 0;
+        case GEVD_OPT_TIMING:
+            h->timing = value ? 1 : 0;
+            if (h->timing && !h->ev_made) {
+                (void)hipSetDevice(h->device);
+                for (auto& e : h->ev)
+                    if (hipEventCreate(&e) != hipSuccess) return GEVD_E_HIP;
+                h->ev_made = true;
+            }
+            return 0;
+        case GEVD_OPT_LEAF:
+            if (value != 0 && (value < 4 || value > 64)) return -3;
+            h->leaf_opt = value;
+            return 0;
+        default:
+            return -2;
+    }
+}
+
+const char* gevd_strerror(int code) {
+    if (code == 0) return "success";
+    if (code > 0) return "S is not positive definite (leading minor reported by the return value)";
+    switch (code) {
+        case GEVD_E_NONFINITE: return "non-finite value in H or S";
+        case GEVD_E_NOCONV: return "tridiagonal eigensolver did not converge";
+        case GEVD_E_NOMEM: return "out of device memory";
+        case GEVD_E_HIP: return "HIP runtime error";
+        case GEVD_E_STATE: return "invalid call order";
+        case GEVD_E_HANG: return "device-side wait exceeded its bound";
+        default: return "invalid argument (the negated return value is its 1-based position)";
+    }
+}
+
+size_t gevd_workspace_bytes(int dtype, int n, int nev) {
+    if (bad_dtype(dtype) || n < 1 || nev < 1 || nev > n) return 0;
+    gevd_ctx tmp;
+    return dtype == GEVD_REAL ? plan_solve<double>(&tmp, n, nev) : plan_solve<zdouble>(&tmp, n, nev);
+}
+
+int gevd_solve(gevd_handle h, int dtype, int n, int nev, void* H, int ldh, void* S, int lds, double* eval, void* C,
+               int ldc) {
+    if (!h) return -1;
+    if (bad_dtype(dtype)) return -2;
+    if (n < 1) return -3;
+    if (nev < 1 || nev > n) return -4;
+    if (!H) return -5;
+    if (ldh < n) return -6;
+    if (!S) return -7;
+    if (lds < n) return -8;
+    if (!eval) return -9;
+    if (!C) return -10;
+    if (ldc < n) return -11;
+    if (hipSetDevice(h->device) != hipSuccess) return GEVD_E_HIP;
+    if (dtype == GEVD_REAL)
+        return do_solve<double>(h, n, nev, (double*)H, ldh, (double*)S, lds, eval, (double*)C, ldc);
+    return do_solve<zdouble>(h, n, nev, (zdouble*)H, ldh, (zdouble*)S, lds, eval, (zdouble*)C, ldc);
+}
+
+int gevd_cholesky(gevd_handle h, int dtype, int n, void* S, int lds) {
+    if (!h) return -1;
+    if (bad_dtype(dtype)) return -2;
+    if (n < 1) return -3;
+    if (!S) return -4;
+    if (lds < n) return -5;
+    if (hipSetDevice(h->device) != hipSuccess) return GEVD_E_HIP;
+    int rc = ensure_ws(h, dtype == GEVD_REAL ? plan_cholesky<double>(n) : plan_cholesky<zdouble>(n));
+    if (rc) return rc;
+    if ((rc = clear_flags(h))) return rc;
+    rc = dtype == GEVD_REAL ? do_cholesky<double>(h, n, (double*)S, lds, h->ws)
+                            : do_cholesky<zdouble>(h, n, (zdouble*)S, lds, h->ws);
+    if (rc) return rc;
+    int fl[NFLAGS];
+    if ((rc = read_flags(h, fl))) return rc;
+    return fl[F_INFO];
+}
+
+int gevd_invert_upper(gevd_handle h, int dtype, int n, const void* U, int ldu, void* Uinv, int ldi) {
+    if (!h) return -1;
+    if (bad_dtype(dtype)) return -2;
+    if (n < 1) return -3;
+    if (!U) return -4;
+    if (ldu < n) return -5;
+    if (!Uinv) return -6;
+    if (ldi < n) return -7;
+    if (hipSetDevice(h->device) != hipSuccess) return GEVD_E_HIP;
+    int rc = ensure_ws(h, dtype == GEVD_REAL ? plan_invert<double>(n) : plan_invert<zdouble>(n));
+    if (rc) return rc;
+    return dtype == GEVD_REAL ? do_invert<double>(h, n, (const double*)U, ldu, (double*)Uinv, ldi, h->ws)
+                              : do_invert<zdouble>(h, n, (const zdouble*)U, ldu, (zdouble*)Uinv, ldi, h->ws);
+}
+
+int gevd_reduce(gevd_handle h, int dtype, int n, void* H, int ldh, const void* Uinv, int ldi, void* A, int lda) {
+    if (!h) return -1;
+    if (bad_dtype(dtype)) return -2;
+    if (n < 1) return -3;
+    if (!H) return -4;
+    if (ldh < n) return -5;
+    if (!Uinv) return -6;
+    if (ldi < n) return -7;
+    if (!A) return -8;
+    if (lda < n) return -9;
+    if (hipSetDevice(h->device) != hipSuccess) return GEVD_E_HIP;
+    int rc = ensure_ws(h, dtype == GEVD_REAL ? plan_reduce<double>(n) : plan_reduce<zdouble>(n));
+    if (rc) return rc;
+    return dtype == GEVD_REAL
+               ? do_reduce<double>(h, n, (double*)H, ldh, (const double*)Uinv, ldi, (double*)A, lda, h->ws)
+               : do_reduce<zdouble>(h, n, (zdouble*)H, ldh, (const zdouble*)Uinv, ldi, (zdouble*)A, lda, h->ws);
+}
+
+int gevd_backtransform(gevd_handle h, int dtype, int n, int nev, const void* Uinv, int ldi, const void* Ct, int ldct,
+                       void* C, int ldc) {
+    if (!h) return -1;
+    if (bad_dtype(dtype)) return -2;
+    if (n < 1) return -3;
+    if (nev < 1 || nev > n) return -4;
+    if (!Uinv) return -5;
+    if (ldi < n) return -6;
+    if (!Ct) return -7;
+    if (ldct < n) return -8;
+    if (!C) return -9;
+    if (ldc < n) return -10;
+    if (hipSetDevice(h->device) != hipSuccess) return GEVD_E_HIP;
+    return dtype == GEVD_REAL
+               ? do_backtransform<double>(h, n, nev, (const double*)Uinv, ldi, (const double*)Ct, ldct, (double*)C, ldc)
+               : do_backtransform<zdouble>(h, n, nev, (const zdouble*)Uinv, ldi, (const zdouble*)Ct, ldct,
+                                           (zdouble*)C, ldc);
+}
+
+int gevd_eigh(gevd_handle h, int dtype, int n, int nev, void* A, int lda, double* eval, void* Z, int ldz) {
+    if (!h) return -1;
+    if (bad_dtype(dtype)) return -2;
+    if (n < 1) return -3;
+    if (nev < 1 || nev > n) return -4;
+    if (!A) return -5;
+    if (lda < n) return -6;
+    if (!eval) return -7;
+    if (!Z) return -8;
+    if (ldz < n) return -9;
+    if (hipSetDevice(h->device) != hipSuccess) return GEVD_E_HIP;
+    int b = pick_band(h, n);
+    size_t need = dtype == GEVD_REAL ? eigh_ws_bytes<double>(n, nev, b, h->leaf_opt)
+                                     : eigh_ws_bytes<zdouble>(n, nev, b, h->leaf_opt);
+    int rc = ensure_ws(h, need);
+    if (rc) return rc;
+    if ((rc = clear_flags(h))) return rc;
+    h->ev_valid = false;
+    mark(h, GEVD_PH_BAND);
+    rc = dtype == GEVD_REAL ? do_eigh<double>(h, n, nev, (double*)A, lda, eval, (double*)Z, ldz, h->ws, true)
+                            : do_eigh<zdouble>(h, n, nev, (zdouble*)A, lda, eval, (zdouble*)Z, ldz, h->ws, true);
+    if (rc) return rc;
+    mark(h, GEVD_PH_MULT);
+    mark(h, GEVD_NPHASE);
+    int fl[NFLAGS];
+    if ((rc = read_flags(h, fl))) return rc;
+    if (fl[F_HANG]) return GEVD_E_HANG;
+    if (fl[F_NOCONV]) return GEVD_E_NOCONV;
+    return 0;
+}
+
+int gevd_get_band(gevd_handle h, int dtype, int n) {
+    if (!h) return -1;
+    if (bad_dtype(dtype)) return -2;
+    if (n < 1) return -3;
+    return pick_band(h, n);
+}
+
+int gevd_band(gevd_handle h, int dtype, int n, void* A, int lda, void* Bd, int ldb) {
+    if (!h) return -1;
+    if (bad_dtype(dtype)) return -2;
+    if (n < 1) return -3;
+    if (!A) return -4;
+    if (lda < n) return -5;
+    if (!Bd) return -6;
+    int b = pick_band(h, n);
+    if (ldb < b + 1) return -7;
+    if (hipSetDevice(h->device) != hipSuccess) return GEVD_E_HIP;
+    size_t need = dtype == GEVD_REAL ? band_ws_bytes<double>(n, b) : band_ws_bytes<zdouble>(n, b);
+    int rc = ensure_ws(h, need);
+    if (rc) return rc;
+    StageCtx sc{h->stream, h->flags + F_NOCONV, h->flags + F_HANG, b, h->leaf_opt};
+    return dtype == GEVD_REAL ? band_run<double>(sc, n, (double*)A, lda, (double*)Bd, ldb, h->ws)
+                              : band_run<zdouble>(sc, n, (zdouble*)A, lda, (zdouble*)Bd, ldb, h->ws);
+}
+
+int gevd_tridiagonalize(gevd_handle h, int dtype, int n, void* A, int lda, double* d, double* e) {
+    if (!h) return -1;
+    if (bad_dtype(dtype)) return -2;
+    if (n < 1) return -3;
+    if (!A) return -4;
+    if (lda < n) return -5;
+    if (!d) return -6;
+    if (!e && n > 1) return -7;
+    if (hipSetDevice(h->device) != hipSuccess) return GEVD_E_HIP;
+    int b = pick_band(h, n);
+    size_t need = dtype == GEVD_REAL ? eigh_ws_bytes<double>(n, 1, b, h->leaf_opt)
+                                     : eigh_ws_bytes<zdouble>(n, 1, b, h->leaf_opt);
+    int rc = ensure_ws(h, need);
+    if (rc) return rc;
+    if ((rc = clear_flags(h))) return rc;
+    StageCtx sc{h->stream, h->flags + F_NOCONV, h->flags + F_HANG, b, h->leaf_opt};
+    rc = dtype == GEVD_REAL ? tridiag_run<double>(sc, n, (double*)A, lda, d, e, h->ws)
+                            : tridiag_run<zdouble>(sc, n, (zdouble*)A, lda, d, e, h->ws);
+    if (rc) return rc;
+    int fl[NFLAGS];
+    if ((rc = read_flags(h, fl))) return rc;
+    if (fl[F_HANG]) return GEVD_E_HANG;
+    return 0;
+}
+
+int gevd_stedc(gevd_handle h, int n, int nev, const double* d, const double* e, double* eval, double* Z, int ldz) {
+    if (!h) return -1;
+    if (n < 1) return -2;
+    if (nev < 1 || nev > n) return -3;
+    if (!d) return -4;
+    if (!e && n > 1) return -5;
+    if (!eval) return -6;
+    if (!Z) return -7;
+    if (ldz < n) return -8;
+    if (hipSetDevice(h->device) != hipSuccess) return GEVD_E_HIP;
+    int rc = ensure_ws(h, stedc_ws_bytes(n, nev, h->leaf_opt));
+    if (rc) return rc;
+    if ((rc = clear_flags(h))) return rc;
+    StageCtx sc{h->stream, h->flags + F_NOCONV, h->flags + F_HANG, 0, h->leaf_opt};
+    rc = stedc_run(sc, n, nev, d, e, eval, Z, ldz, h->ws);
+    if (rc) return rc;
+    int fl[NFLAGS];
+    if ((rc = read_flags(h, fl))) return rc;
+    if (fl[F_NOCONV]) return GEVD_E_NOCONV;
+    return 0;
+}
+
+int gevd_get_timings(gevd_handle h, double* ms, int nphase) {
+    if (!h) return -1;
+    if (!ms) return -2;
+    if (nphase < 1) return -3;
+    if (!h->ev_valid) return GEVD_E_STATE;
+    GEVD_HIP(hipEventSynchronize(h->ev[GEVD_NPHASE]));
+    for (int p = 0; p < nphase && p < GEVD_NPHASE; ++p) {
+        float t = 0.f;
+        GEVD_HIP(hipEventElapsedTime(&t, h->ev[p], h->ev[p + 1]));
+        ms[p] = t;
+    }
+    return 0;
+}
+
+}  // extern "C"

@@ -1,0 +1,302 @@
+// First stage of the two-stage reduction (the route the paper recommends for
+// subsets of eigenvectors, section "ELPA - Usability"): full Hermitian A ->
+// Hermitian band B of half-bandwidth b, A = Q1 B Q1^H.
+//
+// For each panel of b columns starting at column c, the m x b block below
+// the band (rows c+b .. n-1) is QR-factored by Householder reflectors
+// H_s = I - tau_s v_s v_s^H (beta real), then the trailing m x m block is
+// updated two-sidedly with the compact WY form Q = I - V T V^H:
+//   X = A22 V T,  W = X - 1/2 V (T^H V^H X),  A22 <- A22 - W V^H - V W^H,
+// all as MFMA products.  The panel QR is latency-bound: each column costs two
+// row-parallel launches whose reductions finish in the last workgroup to
+// arrive (fixed summation order, so results are deterministic).
+#include "stages.hpp"
+
+namespace gevd {
+namespace {
+
+constexpr int PT = 256;    // threads per panel workgroup = rows per workgroup
+constexpr int MAXB = 64;  // largest supported band
+
+template <typename T>
+struct PanelScratch {
+    T tau[MAXB];
+    T w[MAXB];
+    T scale;
+    double beta;
+    unsigned counter;
+};
+
+template <typename T>
+__device__ inline void make_reflector(T alpha, double xn2, T* tau, T* scale, double* beta) {
+    const double ar = realp(alpha), ai = imagp(alpha);
+    if (xn2 == 0.0 && ai == 0.0) {
+        *tau = zero_of<T>();
+        *scale = zero_of<T>();
+        *beta = ar;
+        return;
+    }
+    const double nrm = sqrt(ar * ar + ai * ai + xn2);
+    const double bt = ar >= 0.0 ? -nrm : nrm;
+    *tau = div_r(from_real<T>(bt) - alpha, bt);
+    *scale = div_s(from_real<T>(1.0), alpha - from_real<T>(bt));
+    *beta = bt;
+}
+
+// Column s of the panel: v_s (into Vp, with v[s] = 1 and zeros above), the
+// products w_j = v_s^H P[:, j] for j > s, and P[s, s] = beta_s.
+template <typename T>
+__global__ __launch_bounds__(PT) void panel_apply(T* P, long lda, int m, int b, int s, T* Vp,
+                                                  PanelScratch<T>* ps, T* partial) {
+    __shared__ T red[PT / WAVE][MAXB];
+    __shared__ int last;
+    const int tid = threadIdx.x;
+    const int r = s + blockIdx.x * PT + tid;
+    const T scale = ps->scale;
+    T v = zero_of<T>();
+    if (r < m) {
+        v = (r == s) ? from_real<T>(1.0) : P[IDX(r, s, lda)] * scale;
+        Vp[IDX(r, s, m)] = v;
+    }
+    if (blockIdx.x == 0)
+        for (int i = tid; i < s; i += PT) Vp[IDX(i, s, m)] = zero_of<T>();
+    const int w = tid / WAVE, l = tid % WAVE;
+    const T cv = conjg(v);
+    for (int j = s + 1; j < b; ++j) {
+        T x = (r < m) ? cv * P[IDX(r, j, lda)] : zero_of<T>();
+        x = wave_sum(x);
+        if (l == 0) red[w][j] = x;
+    }
+    __syncthreads();
+    if (tid > s && tid < b) {
+        T acc = red[0][tid];
+        for (int q = 1; q < PT / WAVE; ++q) acc += red[q][tid];
+        partial[(size_t)blockIdx.x * b + tid] = acc;
+    }
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) last = (atomicAdd(&ps->counter, 1u) == gridDim.x - 1);
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    if (tid > s && tid < b) {
+        T acc = zero_of<T>();
+        for (unsigned g = 0; g < gridDim.x; ++g) acc += partial[(size_t)g * b + tid];
+        ps->w[tid] = acc;
+    }
+    if (tid == 0) {
+        ps->counter = 0;
+        P[IDX(s, s, lda)] = from_real<T>(ps->beta);
+    }
+}
+
+// Rank-1 update of the columns right of s with reflector s (if s >= 0),
+// then the norm of column s+1 below its diagonal and reflector s+1 (if
+// s+1 < nref), finished by the last workgroup.
+template <typename T>
+__global__ __launch_bounds__(PT) void panel_update(T* P, long lda, int m, int b, int s, int nref, const T* Vp,
+                                                   PanelScratch<T>* ps, double* partial) {
+    __shared__ double red[PT / WAVE];
+    __shared__ int last;
+    const int tid = threadIdx.x;
+    const int r0 = s < 0 ? 0 : s;
+    const int r = r0 + blockIdx.x * PT + tid;
+    const int nx = s + 1;
+    if (s >= 0 && r < m) {
+        const T ctv = conjg(ps->tau[s]) * Vp[IDX(r, s, m)];
+        for (int j = s + 1; j < b; ++j) P[IDX(r, j, lda)] -= ctv * ps->w[j];
+    }
+    if (nx >= nref) return;
+    double x = (r > nx && r < m) ? abs2(P[IDX(r, nx, lda)]) : 0.0;
+    x = block_sum<PT>(x, red);
+    if (tid == 0) partial[blockIdx.x] = x;
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) last = (atomicAdd(&ps->counter, 1u) == gridDim.x - 1);
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    if (tid == 0) {
+        double xn2 = 0.0;
+        for (unsigned g = 0; g < gridDim.x; ++g) xn2 += partial[g];
+        T tau, scale;
+        double beta;
+        make_reflector<T>(P[IDX(nx, nx, lda)], xn2, &tau, &scale, &beta);
+        ps->tau[nx] = tau;
+        ps->scale = scale;
+        ps->beta = beta;
+        ps->counter = 0;
+    }
+}
+
+// T (b x b upper) of Q = H_0 ... H_{b-1} = I - V T V^H from the Gram matrix
+// G = V^H V: T[s, s] = tau_s, T[0:s, s] = -tau_s T[0:s, 0:s] G[0:s, s].
+template <typename T>
+__global__ __launch_bounds__(MAXB) void tfactor_kernel(int b, const T* G, const PanelScratch<T>* ps, T* Tf) {
+    __shared__ T t[MAXB][MAXB + 1];
+    const int i = threadIdx.x;
+    for (int s = 0; s < b; ++s) {
+        const T ts = ps->tau[s];
+        if (i < s) {
+            T acc = zero_of<T>();
+            for (int l = i; l < s; ++l) acc += t[i][l] * G[IDX(l, s, b)];
+            t[i][s] = -(ts * acc);
+        } else if (i == s) {
+            t[i][s] = ts;
+        } else if (i < b) {
+            t[i][s] = zero_of<T>();
+        }
+        __syncthreads();
+    }
+    if (i < b)
+        for (int s = 0; s < b; ++s) Tf[IDX(i, s, b)] = t[i][s];
+}
+
+// Band in lower band storage from the reduced A: columns of processed panels
+// take the (final) diagonal block and the R factor, zero below R's diagonal.
+template <typename T>
+__global__ void extract_band(int n, int b, int np, const T* A, long lda, T* Bd, long ldb) {
+    long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long long)ldb * n) return;
+    const int rho = (int)(idx % ldb), j = (int)(idx / ldb);
+    const int i = j + rho;
+    T val = zero_of<T>();
+    if (rho <= b && i < n) {
+        const int p = j / b, cp = p * b;
+        val = A[IDX(i, j, lda)];
+        if (p < np && i >= cp + b && (i - cp - b) > (j - cp)) val = zero_of<T>();
+        if (rho == 0) val = from_real<T>(realp(val));
+    }
+    Bd[IDX(rho, j, ldb)] = val;
+}
+
+struct Carve {
+    char* p;
+    size_t off = 0;
+    template <typename U>
+    U* take(size_t elems) {
+        off = (off + 255) & ~size_t(255);
+        U* r = reinterpret_cast<U*>(p ? p + off : nullptr);
+        off += elems * sizeof(U);
+        return r;
+    }
+};
+
+constexpr int SK = 4;  // split of the long inner dimension in panel products
+
+int count_panels(int n, int b) {
+    int np = 0;
+    while (n - np * b - b >= 2) ++np;
+    return np;
+}
+
+template <typename T>
+struct He2hbWs {
+    T *Y, *skY, *LR, *G, *M1, *M2, *skS, *partialT;
+    double* partialD;
+    PanelScratch<T>* ps;
+};
+
+template <typename T>
+size_t carve_ws(char* base, int n, int b, He2hbWs<T>* w) {
+    Carve c{base};
+    const size_t nb = (size_t)n * b;
+    He2hbWs<T> t;
+    t.Y = c.take<T>(nb);
+    t.skY = c.take<T>(SK * nb);
+    t.LR = c.take<T>(3 * nb);
+    t.G = c.take<T>((size_t)b * b);
+    t.M1 = c.take<T>((size_t)b * b);
+    t.M2 = c.take<T>((size_t)b * b);
+    t.skS = c.take<T>((size_t)SK * b * b);
+    const size_t nwg = (size_t)(n + PT - 1) / PT + 1;
+    t.partialT = c.take<T>(nwg * b);
+    t.partialD = c.take<double>(nwg);
+    t.ps = c.take<PanelScratch<T>>(1);
+    if (w) *w = t;
+    return c.off;
+}
+
+}  // namespace
+
+template <typename T>
+size_t he2hb_ws_elems(int n, int b) {
+    return (carve_ws<T>(nullptr, n, b, nullptr) + sizeof(T) - 1) / sizeof(T);
+}
+
+template <typename T>
+int he2hb(const StageCtx& c, int n, T* A, long lda, BandRefl<T>& R, T* Bd, long ldb, T* work) {
+    hipStream_t st = c.st;
+    const int b = R.b;
+    const int np = count_panels(n, b);
+    R.n = n;
+    R.np = np;
+    He2hbWs<T> w;
+    carve_ws<T>(reinterpret_cast<char*>(work), n, b, &w);
+    const T one = from_real<T>(1.0), mone = from_real<T>(-1.0), zero = zero_of<T>();
+    const T mhalf = from_real<T>(-0.5);
+    int rc;
+    // the panel scratch counter must start at zero
+    if ((rc = set_zero<T>(st, (int)((sizeof(PanelScratch<T>) + sizeof(T) - 1) / sizeof(T)), 1, (T*)w.ps, 1)))
+        return rc;
+    for (int p = 0; p < np; ++p) {
+        const int c0 = p * b;
+        const int m = n - c0 - b;
+        const int nref = min(b, m - 1);
+        T* P = A + IDX(c0 + b, c0, lda);
+        T* Vp = R.V + R.voff(p);
+        T* Tp = R.Tf + (size_t)p * b * b;
+        if ((rc = set_zero<T>(st, m, b, Vp, m))) return rc;
+        // reflector 0
+        hipLaunchKernelGGL(panel_update<T>, dim3((m + PT - 1) / PT), dim3(PT), 0, st, P, lda, m, b, -1, nref,
+                           (const T*)Vp, w.ps, w.partialD);
+        GEVD_LAUNCH_CHECK();
+        for (int s = 0; s < nref; ++s) {
+            const int rows = m - s;
+            const unsigned g = (unsigned)((rows + PT - 1) / PT);
+            hipLaunchKernelGGL(panel_apply<T>, dim3(g), dim3(PT), 0, st, P, lda, m, b, s, Vp, w.ps, w.partialT);
+            GEVD_LAUNCH_CHECK();
+            hipLaunchKernelGGL(panel_update<T>, dim3(g), dim3(PT), 0, st, P, lda, m, b, s, nref, (const T*)Vp, w.ps,
+                               w.partialD);
+            GEVD_LAUNCH_CHECK();
+        }
+        // T factor from G = V^H V
+        if ((rc = gemm<T>(st, OP_C, OP_N, b, b, m, one, Vp, m, Vp, m, zero, w.G, b, K_FULL, T_ALL, Batch(), SK,
+                          w.skS)))
+            return rc;
+        hipLaunchKernelGGL(tfactor_kernel<T>, dim3(1), dim3(MAXB), 0, st, b, (const T*)w.G, (const PanelScratch<T>*)w.ps,
+                           Tp);
+        GEVD_LAUNCH_CHECK();
+        // two-sided update of A22 = A[c0+b:, c0+b:]
+        T* A22 = A + IDX(c0 + b, c0 + b, lda);
+        T* Wb = w.LR;                  // columns [0, b): W
+        T* Vb = w.LR + (size_t)m * b;  // columns [b, 2b): V
+        T* W2 = w.LR + (size_t)2 * m * b;  // columns [2b, 3b): W again
+        if ((rc = gemm<T>(st, OP_N, OP_N, m, b, m, one, A22, lda, Vp, m, zero, w.Y, m, K_FULL, T_ALL, Batch(),
+                          m >= 2048 ? SK : 1, w.skY)))
+            return rc;
+        if ((rc = gemm<T>(st, OP_N, OP_N, m, b, b, one, w.Y, m, Tp, b, zero, Wb, m, K_B_UPPER))) return rc;  // X
+        if ((rc = gemm<T>(st, OP_C, OP_N, b, b, m, one, Vp, m, Wb, m, zero, w.M1, b, K_FULL, T_ALL, Batch(), SK,
+                          w.skS)))
+            return rc;
+        if ((rc = gemm<T>(st, OP_C, OP_N, b, b, b, one, Tp, b, w.M1, b, zero, w.M2, b, K_A_LOWER))) return rc;
+        if ((rc = gemm<T>(st, OP_N, OP_N, m, b, b, mhalf, Vp, m, w.M2, b, one, Wb, m))) return rc;  // W
+        if ((rc = copy_matrix<T>(st, m, b, Wb, m, W2, m))) return rc;
+        if ((rc = copy_matrix<T>(st, m, b, Vp, m, Vb, m))) return rc;
+        if ((rc = gemm<T>(st, OP_N, OP_C, m, m, 2 * b, mone, w.LR, m, Vb, m, one, A22, lda))) return rc;
+    }
+    const long long tot = (long long)ldb * n;
+    hipLaunchKernelGGL(extract_band<T>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, n, b, np, (const T*)A,
+                       lda, Bd, ldb);
+    GEVD_LAUNCH_CHECK();
+    return 0;
+}
+
+#define INST(T)                                                                                  \
+    template size_t he2hb_ws_elems<T>(int, int);                                                 \
+    template int he2hb<T>(const StageCtx&, int, T*, long, BandRefl<T>&, T*, long, T*);
+INST(double)
+INST(zdouble)
+#undef INST
+
+}  // namespace gevd

@@ -1,0 +1,180 @@
+// Step 1 (Cholesky S = U^H U) and step 2 (U -> U^{-1}) of the reduction to
+// standard form (paper, section "Solving the generalized eigenproblem").
+//
+// Cholesky is blocked right-looking over 64-column panels: a one-workgroup
+// kernel factors the 64 x 64 diagonal block in LDS and also inverts it; the
+// row panel U12 = U11^{-H} S12 then is one MFMA product with that inverse
+// (no triangular solve on the critical path), and the trailing update
+// S22 -= U12^H U12 is an MFMA product restricted to upper tiles.
+//
+// The inverse is formed recursively: inv([A B; 0 D]) = [Ai, -Ai B Di; 0, Di],
+// with all 64 x 64 diagonal blocks inverted by one batched launch and every
+// off-diagonal block produced by two triangular MFMA products.
+#include "kernels.hpp"
+
+namespace gevd {
+namespace {
+
+constexpr int NB = 64;
+constexpr int NTD = 256;
+
+// Factor the jb x jb upper block at S (ld lds) in place; write its inverse to
+// Winv (ld NB, zeros below the diagonal).  *info is set to the global
+// 1-based minor (gofs + k + 1) of the first non-positive or non-finite pivot.
+template <typename T>
+__global__ __launch_bounds__(NTD) void potrf_diag_kernel(int jb, T* S, long lds, T* Winv, int* info, int gofs) {
+    __shared__ T a[NB][NB + 1];  // a[r][c], upper triangle used
+    __shared__ T x[NB][NB + 1];  // the inverse, by columns
+    __shared__ int bad;
+    if (*info != 0) return;  // an earlier panel already failed
+    const int t = threadIdx.x;
+    if (t == 0) bad = 0;
+    for (int e = t; e < jb * jb; e += NTD) {
+        int r = e % jb, c = e / jb;
+        a[r][c] = (r <= c) ? S[IDX(r, c, lds)] : zero_of<T>();
+    }
+    __syncthreads();
+    for (int k = 0; k < jb; ++k) {
+        if (t == 0) {
+            double d = realp(a[k][k]);
+            if (!(d > 0.0) || !isfinite(d)) {
+                bad = 1;
+                atomicCAS(info, 0, gofs + k + 1);
+            } else {
+                a[k][k] = from_real<T>(sqrt(d));
+            }
+        }
+        __syncthreads();
+        if (bad) return;
+        const double ukk = realp(a[k][k]);
+        for (int c = k + 1 + t; c < jb; c += NTD) a[k][c] = div_r(a[k][c], ukk);
+        __syncthreads();
+        // trailing: a[r][c] -= conj(a[k][r]) a[k][c], k < r <= c
+        const int m = jb - k - 1;
+        for (int e = t; e < m * m; e += NTD) {
+            int r = k + 1 + e % m, c = k + 1 + e / m;
+            if (r <= c) a[r][c] -= conjg(a[k][r]) * a[k][c];
+        }
+        __syncthreads();
+    }
+    // write U11 (upper triangle only)
+    for (int e = t; e < jb * jb; e += NTD) {
+        int r = e % jb, c = e / jb;
+        if (r <= c) S[IDX(r, c, lds)] = a[r][c];
+    }
+    // inverse by columns: thread c solves U x = e_c
+    if (t < jb) {
+        const int c = t;  // this thread owns column c of the inverse
+        for (int i = c + 1; i < NB; ++i) x[i][c] = zero_of<T>();
+        x[c][c] = from_real<T>(1.0 / realp(a[c][c]));
+        for (int i = c - 1; i >= 0; --i) {
+            T s = zero_of<T>();
+            for (int l = i + 1; l <= c; ++l) s += a[i][l] * x[l][c];
+            x[i][c] = div_r(-s, realp(a[i][i]));
+        }
+        for (int i = 0; i < jb; ++i) Winv[IDX(i, c, NB)] = x[i][c];
+    }
+}
+
+// Batched inverse of the diagonal NB x NB blocks of upper triangular U:
+// block b covers rows/cols [b*NB, min(n, (b+1)*NB)).  Writes the inverse
+// into the same position of Uinv (zeros below the diagonal).
+template <typename T>
+__global__ __launch_bounds__(NTD) void diag_inv_kernel(int n, const T* U, long ldu, T* Uinv, long ldi) {
+    __shared__ T a[NB][NB + 1];
+    __shared__ T x[NB][NB + 1];
+    const int o = blockIdx.x * NB;
+    const int jb = min(NB, n - o);
+    const int t = threadIdx.x;
+    for (int e = t; e < jb * jb; e += NTD) {
+        int r = e % jb, c = e / jb;
+        a[r][c] = (r <= c) ? U[IDX(o + r, o + c, ldu)] : zero_of<T>();
+    }
+    __syncthreads();
+    if (t < jb) {
+        const int c = t;  // this thread owns column c of the inverse
+        for (int i = c + 1; i < NB; ++i) x[i][c] = zero_of<T>();
+        x[c][c] = from_real<T>(1.0 / realp(a[c][c]));
+        for (int i = c - 1; i >= 0; --i) {
+            T s = zero_of<T>();
+            for (int l = i + 1; l <= c; ++l) s += a[i][l] * x[l][c];
+            x[i][c] = div_r(-s, realp(a[i][i]));
+        }
+        for (int i = 0; i < jb; ++i) Uinv[IDX(o + i, o + c, ldi)] = x[i][c];
+    }
+}
+
+template <typename T>
+int trtri_rec(hipStream_t st, int o, int s, const T* U, long ldu, T* Uinv, long ldi, T* tmp) {
+    if (s <= NB) return 0;  // leaves done by the batched kernel
+    int s1 = ((s / 2 + NB - 1) / NB) * NB;
+    int s2 = s - s1;
+    int rc = trtri_rec(st, o, s1, U, ldu, Uinv, ldi, tmp);
+    if (rc) return rc;
+    rc = trtri_rec(st, o + s1, s2, U, ldu, Uinv, ldi, tmp);
+    if (rc) return rc;
+    const T one = from_real<T>(1.0), mone = from_real<T>(-1.0), zero = zero_of<T>();
+    // tmp = U12 * Uinv22   (s1 x s2), Uinv22 upper triangular
+    rc = gemm<T>(st, OP_N, OP_N, s1, s2, s2, one, U + IDX(o, o + s1, ldu), ldu, Uinv + IDX(o + s1, o + s1, ldi),
+                 ldi, zero, tmp, s1, K_B_UPPER);
+    if (rc) return rc;
+    // Uinv12 = -Uinv11 * tmp, Uinv11 upper triangular
+    return gemm<T>(st, OP_N, OP_N, s1, s2, s1, mone, Uinv + IDX(o, o, ldi), ldi, tmp, s1, zero,
+                   Uinv + IDX(o, o + s1, ldi), ldi, K_A_UPPER);
+}
+
+}  // namespace
+
+template <typename T>
+size_t potrf_work_elems(int) {
+    return (size_t)NB * NB;
+}
+template <typename T>
+size_t trtri_work_elems(int n) {
+    size_t h = (size_t)(n / 2 + NB);
+    return h * h;
+}
+
+template <typename T>
+int potrf(hipStream_t st, int n, T* S, long lds, T* work, int* info_dev) {
+    const T one = from_real<T>(1.0), mone = from_real<T>(-1.0), zero = zero_of<T>();
+    for (int j = 0; j < n; j += NB) {
+        const int jb = min(NB, n - j);
+        hipLaunchKernelGGL(potrf_diag_kernel<T>, dim3(1), dim3(NTD), 0, st, jb, S + IDX(j, j, lds), lds, work,
+                           info_dev, j);
+        GEVD_LAUNCH_CHECK();
+        const int m2 = n - j - jb;
+        if (m2 <= 0) break;
+        T* S12 = S + IDX(j, j + jb, lds);
+        // U12 = inv(U11)^H S12, in place: the product's row count jb <= 64
+        // is a single tile row, so every workgroup reads its whole column
+        // slab of S12 before it writes that slab.
+        int rc = gemm<T>(st, OP_C, OP_N, jb, m2, jb, one, work, NB, S12, lds, zero, S12, lds, K_A_LOWER);
+        if (rc) return rc;
+        // S22 -= U12^H U12 on the upper tiles
+        rc = gemm<T>(st, OP_C, OP_N, m2, m2, jb, mone, S12, lds, S12, lds, one, S + IDX(j + jb, j + jb, lds), lds,
+                     K_FULL, T_UPPER_TILES);
+        if (rc) return rc;
+    }
+    return 0;
+}
+
+template <typename T>
+int trtri(hipStream_t st, int n, const T* U, long ldu, T* Uinv, long ldi, T* work) {
+    int rc = set_zero<T>(st, n, n, Uinv, ldi);
+    if (rc) return rc;
+    hipLaunchKernelGGL(diag_inv_kernel<T>, dim3((n + NB - 1) / NB), dim3(NTD), 0, st, n, U, ldu, Uinv, ldi);
+    GEVD_LAUNCH_CHECK();
+    return trtri_rec<T>(st, 0, n, U, ldu, Uinv, ldi, work);
+}
+
+#define INST(T)                                                              \
+    template size_t potrf_work_elems<T>(int);                                \
+    template size_t trtri_work_elems<T>(int);                                \
+    template int potrf<T>(hipStream_t, int, T*, long, T*, int*);             \
+    template int trtri<T>(hipStream_t, int, const T*, long, T*, long, T*);
+INST(double)
+INST(zdouble)
+#undef INST
+
+}  // namespace gevd

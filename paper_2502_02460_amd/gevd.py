@@ -1,0 +1,244 @@
+"""Python binding of libgevd.so (argument marshalling only).
+
+Every step of the solve runs in the HIP kernels of libgevd.so; this module
+passes torch tensors' device pointers and the current HIP stream through the
+C interface declared in include/gevd.h, and turns nonzero return codes into
+exceptions.  There is no CPU fallback: without the built library on a GPU
+machine every call raises.
+
+Matrices are column-major (Fortran order): a tensor M with M.stride(0) == 1
+and M.stride(1) >= n.  ``colmajor(x)`` makes such a copy of any 2-D tensor.
+Real problems are float64, complex problems complex128.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+SO_PATH = os.path.join(_HERE, "libgevd.so")
+
+GEVD_REAL, GEVD_COMPLEX = 0, 1
+OPT_BAND, OPT_TIMING, OPT_LEAF = 1, 2, 3
+PHASES = ("cholesky", "invert", "multiply", "band", "tridiag", "solve", "back2", "back1", "mult")
+E_NONFINITE, E_NOCONV, E_NOMEM, E_HIP, E_STATE, E_HANG = -1001, -1002, -1003, -1004, -1005, -1006
+
+_lib = None
+_lock = threading.Lock()
+
+
+class GevdError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__("%s: %s (code %d)" % (where, strerror(code), code))
+
+
+class NotPositiveDefinite(GevdError):
+    pass
+
+
+def load():
+    """Load libgevd.so (built by paper_2502_02460_amd.build); raise if absent."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(SO_PATH):
+            raise RuntimeError("libgevd.so is not built (run __graft_entry__.build())")
+        L = ctypes.CDLL(SO_PATH)
+        P, I, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+        L.gevd_create.argtypes = [ctypes.POINTER(P), I]
+        L.gevd_destroy.argtypes = [P]
+        L.gevd_set_stream.argtypes = [P, P]
+        L.gevd_set_option.argtypes = [P, I, I]
+        L.gevd_strerror.argtypes = [I]
+        L.gevd_strerror.restype = ctypes.c_char_p
+        L.gevd_workspace_bytes.argtypes = [I, I, I]
+        L.gevd_workspace_bytes.restype = ctypes.c_size_t
+        L.gevd_solve.argtypes = [P, I, I, I, P, I, P, I, P, P, I]
+        L.gevd_cholesky.argtypes = [P, I, I, P, I]
+        L.gevd_invert_upper.argtypes = [P, I, I, P, I, P, I]
+        L.gevd_reduce.argtypes = [P, I, I, P, I, P, I, P, I]
+        L.gevd_eigh.argtypes = [P, I, I, I, P, I, P, P, I]
+        L.gevd_backtransform.argtypes = [P, I, I, I, P, I, P, I, P, I]
+        L.gevd_band.argtypes = [P, I, I, P, I, P, I]
+        L.gevd_get_band.argtypes = [P, I, I]
+        L.gevd_tridiagonalize.argtypes = [P, I, I, P, I, P, P]
+        L.gevd_stedc.argtypes = [P, I, I, P, P, P, P, I]
+        L.gevd_get_timings.argtypes = [P, ctypes.POINTER(D), I]
+        _lib = L
+        return L
+
+
+def strerror(code: int) -> str:
+    return load().gevd_strerror(code).decode()
+
+
+def _check(rc: int, where: str) -> int:
+    if rc > 0:
+        raise NotPositiveDefinite(rc, where)
+    if rc != 0:
+        raise GevdError(rc, where)
+    return rc
+
+
+def colmajor(x: torch.Tensor) -> torch.Tensor:
+    """Column-major copy of a 2-D tensor (same logical values)."""
+    return x.mT.contiguous().mT
+
+
+def _ld(M: torch.Tensor, n_rows: int, name: str) -> int:
+    if M.dim() != 2 or M.stride(0) != 1 or M.stride(1) < max(1, n_rows):
+        raise ValueError("%s must be column-major (stride (1, ld >= %d)), got strides %s" %
+                         (name, n_rows, tuple(M.stride())))
+    if not M.is_cuda:
+        raise ValueError("%s must be a device tensor" % name)
+    return M.stride(1)
+
+
+def _dtype_code(t: torch.Tensor) -> int:
+    if t.dtype == torch.float64:
+        return GEVD_REAL
+    if t.dtype == torch.complex128:
+        return GEVD_COMPLEX
+    raise TypeError("only float64 and complex128 are supported, got %s" % t.dtype)
+
+
+def _empty_cm(rows: int, cols: int, dtype, device) -> torch.Tensor:
+    return torch.empty((cols, rows), dtype=dtype, device=device).mT
+
+
+class Solver:
+    """A library handle bound to one device; keeps its workspace between
+    calls.  Work goes to the current torch stream of that device."""
+
+    def __init__(self, device=None, band: int = 0, leaf: int = 0, timing: bool = False):
+        L = load()
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else
+                                   torch.device(device).index or 0)
+        h = ctypes.c_void_p()
+        _check(L.gevd_create(ctypes.byref(h), self.device.index), "gevd_create")
+        self._h = h
+        if band:
+            _check(L.gevd_set_option(h, OPT_BAND, band), "gevd_set_option")
+        if leaf:
+            _check(L.gevd_set_option(h, OPT_LEAF, leaf), "gevd_set_option")
+        if timing:
+            _check(L.gevd_set_option(h, OPT_TIMING, 1), "gevd_set_option")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().gevd_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _stream(self):
+        s = torch.cuda.current_stream(self.device).cuda_stream
+        load().gevd_set_stream(self._h, ctypes.c_void_p(s))
+
+    # ------------------------------------------------------------------ steps
+    def solve(self, H: torch.Tensor, S: torch.Tensor, nev: int, C: torch.Tensor | None = None,
+              eval_out: torch.Tensor | None = None):
+        """Generalized solve H c = eps S c.  H is clobbered; S's upper triangle
+        receives U.  Returns (eval: all n ascending, C: n x nev)."""
+        n = H.shape[0]
+        t = _dtype_code(H)
+        if S.dtype != H.dtype:
+            raise TypeError("H and S must have the same dtype")
+        ldh, lds = _ld(H, n, "H"), _ld(S, n, "S")
+        if C is None:
+            C = _empty_cm(n, nev, H.dtype, H.device)
+        ldc = _ld(C, n, "C")
+        w = eval_out if eval_out is not None else torch.empty(n, dtype=torch.float64, device=H.device)
+        self._stream()
+        _check(load().gevd_solve(self._h, t, n, nev, H.data_ptr(), ldh, S.data_ptr(), lds, w.data_ptr(),
+                                 C.data_ptr(), ldc), "gevd_solve")
+        return w, C
+
+    def cholesky(self, S: torch.Tensor) -> torch.Tensor:
+        n = S.shape[0]
+        self._stream()
+        _check(load().gevd_cholesky(self._h, _dtype_code(S), n, S.data_ptr(), _ld(S, n, "S")), "gevd_cholesky")
+        return S
+
+    def invert_upper(self, U: torch.Tensor) -> torch.Tensor:
+        n = U.shape[0]
+        Ui = _empty_cm(n, n, U.dtype, U.device)
+        self._stream()
+        _check(load().gevd_invert_upper(self._h, _dtype_code(U), n, U.data_ptr(), _ld(U, n, "U"), Ui.data_ptr(), n),
+               "gevd_invert_upper")
+        return Ui
+
+    def reduce(self, H: torch.Tensor, Uinv: torch.Tensor) -> torch.Tensor:
+        n = H.shape[0]
+        A = _empty_cm(n, n, H.dtype, H.device)
+        self._stream()
+        _check(load().gevd_reduce(self._h, _dtype_code(H), n, H.data_ptr(), _ld(H, n, "H"), Uinv.data_ptr(),
+                                  _ld(Uinv, n, "Uinv"), A.data_ptr(), n), "gevd_reduce")
+        return A
+
+    def eigh(self, A: torch.Tensor, nev: int):
+        n = A.shape[0]
+        w = torch.empty(n, dtype=torch.float64, device=A.device)
+        Z = _empty_cm(n, nev, A.dtype, A.device)
+        self._stream()
+        _check(load().gevd_eigh(self._h, _dtype_code(A), n, nev, A.data_ptr(), _ld(A, n, "A"), w.data_ptr(),
+                                Z.data_ptr(), n), "gevd_eigh")
+        return w, Z
+
+    def backtransform(self, Uinv: torch.Tensor, Ct: torch.Tensor) -> torch.Tensor:
+        n, nev = Ct.shape
+        C = _empty_cm(n, nev, Ct.dtype, Ct.device)
+        self._stream()
+        _check(load().gevd_backtransform(self._h, _dtype_code(Ct), n, nev, Uinv.data_ptr(), _ld(Uinv, n, "Uinv"),
+                                         Ct.data_ptr(), _ld(Ct, n, "Ct"), C.data_ptr(), n), "gevd_backtransform")
+        return C
+
+    def band_width(self, n: int, dtype=torch.float64) -> int:
+        return load().gevd_get_band(self._h, GEVD_COMPLEX if dtype == torch.complex128 else GEVD_REAL, n)
+
+    def band(self, A: torch.Tensor) -> torch.Tensor:
+        """Lower band storage (b+1) x n of the first-stage band matrix."""
+        n = A.shape[0]
+        b = self.band_width(n, A.dtype)
+        Bd = _empty_cm(b + 1, n, A.dtype, A.device)
+        self._stream()
+        _check(load().gevd_band(self._h, _dtype_code(A), n, A.data_ptr(), _ld(A, n, "A"), Bd.data_ptr(), b + 1),
+               "gevd_band")
+        return Bd
+
+    def tridiagonalize(self, A: torch.Tensor):
+        n = A.shape[0]
+        d = torch.empty(n, dtype=torch.float64, device=A.device)
+        e = torch.empty(max(n - 1, 1), dtype=torch.float64, device=A.device)
+        self._stream()
+        _check(load().gevd_tridiagonalize(self._h, _dtype_code(A), n, A.data_ptr(), _ld(A, n, "A"), d.data_ptr(),
+                                          e.data_ptr()), "gevd_tridiagonalize")
+        return d, e[: n - 1]
+
+    def stedc(self, d: torch.Tensor, e: torch.Tensor, nev: int):
+        n = d.shape[0]
+        w = torch.empty(n, dtype=torch.float64, device=d.device)
+        Z = _empty_cm(n, nev, torch.float64, d.device)
+        ee = e if n > 1 else torch.zeros(1, dtype=torch.float64, device=d.device)
+        self._stream()
+        _check(load().gevd_stedc(self._h, n, nev, d.data_ptr(), ee.data_ptr(), w.data_ptr(), Z.data_ptr(), n),
+               "gevd_stedc")
+        return w, Z
+
+    def timings(self) -> dict:
+        arr = (ctypes.c_double * len(PHASES))()
+        _check(load().gevd_get_timings(self._h, arr, len(PHASES)), "gevd_get_timings")
+        return dict(zip(PHASES, list(arr)))
+
+
+def workspace_bytes(dtype, n: int, nev: int) -> int:
+    return int(load().gevd_workspace_bytes(GEVD_COMPLEX if dtype == torch.complex128 else GEVD_REAL, n, nev))
