@@ -63,6 +63,9 @@ size_t carve_eigh(char* base, int n, int nev, int b, int leaf, EighWs<T>* out) {
     w.R2.tmax = tmax;
     w.R2.V2 = c.take<T>((size_t)std::max(tmax, 1) * std::max(nsw, 1) * b);
     w.R2.tau2 = c.take<T>((size_t)std::max(tmax, 1) * std::max(nsw, 1));
+    w.R2.nbs = chase_group<T>();
+    w.R2.nblk = (std::max(nsw, 1) + w.R2.nbs - 1) / w.R2.nbs;
+    w.R2.Tg = c.take<T>((size_t)w.R2.nblk * std::max(tmax, 1) * w.R2.nbs * w.R2.nbs);
     w.d = c.take<double>(n);
     w.e = c.take<double>(n);
     w.sync_area = c.take<int>((size_t)n + 8);

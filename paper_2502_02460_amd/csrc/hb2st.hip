@@ -29,76 +29,55 @@ constexpr long long SPIN_LIMIT = 200000000LL;
 
 __device__ inline int ntasks(int n, int b, int sw) { return (n - 1 - sw + b - 1) / b; }
 
+// Householder reflector for x[0..L-1] (LDS, overwritten by v with v[0] = 1):
+// H^H x = beta e1, beta real; sc[] receives {tau, beta, scale}.  One wave.
 template <typename T>
-__device__ inline void dot_rows(const T (*M)[MAXB + 1], const T* x, T* y, T (*red)[MAXB], int L, int C) {
-    // y[i] = sum_j M[i][j] x[j], i < L, j < C; 4 waves split the columns.
-    const int tid = threadIdx.x, i = tid % MAXB, seg = tid / MAXB;
-    T acc = zero_of<T>();
-    if (i < L)
-        for (int j = seg * 16; j < min(C, seg * 16 + 16); ++j) acc += M[i][j] * x[j];
-    red[seg][i] = acc;
-    __syncthreads();
-    if (tid < L) y[tid] = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
-    __syncthreads();
-}
-
-template <typename T>
-__device__ inline void dot_cols(const T (*M)[MAXB + 1], const T* x, T* z, T (*red)[MAXB], int L, int C) {
-    // z[j] = sum_i conj(x[i]) M[i][j], j < C, i < L.
-    const int tid = threadIdx.x, j = tid % MAXB, seg = tid / MAXB;
-    T acc = zero_of<T>();
-    if (j < C)
-        for (int i = seg * 16; i < min(L, seg * 16 + 16); ++i) acc += conjg(x[i]) * M[i][j];
-    red[seg][j] = acc;
-    __syncthreads();
-    if (tid < C) z[tid] = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
-    __syncthreads();
-}
-
-// Householder reflector for x[0..L-1] (in LDS, overwritten by v with
-// v[0] = 1): H^H x = beta e1, beta real.  Wave 0 computes; the result is
-// broadcast through sc[] = {tau, beta}.
-template <typename T>
-__device__ inline void reflect(T* x, int L, T* sc) {
-    const int tid = threadIdx.x;
-    if (tid < WAVE) {
-        double a2 = (tid >= 1 && tid < L) ? abs2(x[tid]) : 0.0;
-        a2 = wave_sum(a2);
-        if (tid == 0) {
-            const T alpha = x[0];
-            const double ar = realp(alpha), ai = imagp(alpha);
-            if (a2 == 0.0 && ai == 0.0) {
-                sc[0] = zero_of<T>();
-                sc[1] = from_real<T>(ar);
-                sc[2] = zero_of<T>();
-            } else {
-                const double nrm = sqrt(ar * ar + ai * ai + a2);
-                const double bt = ar >= 0.0 ? -nrm : nrm;
-                sc[0] = div_r(from_real<T>(bt) - alpha, bt);
-                sc[1] = from_real<T>(bt);
-                sc[2] = div_s(from_real<T>(1.0), alpha - from_real<T>(bt));
-            }
+__device__ inline void reflect1(T* x, int L, T* sc) {
+    const int lane = threadIdx.x;
+    double a2 = (lane >= 1 && lane < L) ? abs2(x[lane]) : 0.0;
+    a2 = wave_sum(a2);
+    if (lane == 0) {
+        const T alpha = x[0];
+        const double ar = realp(alpha), ai = imagp(alpha);
+        if (a2 == 0.0 && ai == 0.0) {
+            sc[0] = zero_of<T>();
+            sc[1] = from_real<T>(ar);
+            sc[2] = zero_of<T>();
+        } else {
+            const double nrm = sqrt(ar * ar + ai * ai + a2);
+            const double bt = ar >= 0.0 ? -nrm : nrm;
+            sc[0] = div_r(from_real<T>(bt) - alpha, bt);
+            sc[1] = from_real<T>(bt);
+            sc[2] = div_s(from_real<T>(1.0), alpha - from_real<T>(bt));
         }
     }
     __syncthreads();
-    if (tid >= 1 && tid < L) x[tid] = x[tid] * sc[2];
-    if (tid == 0) x[0] = from_real<T>(1.0);
+    if (lane >= 1 && lane < L) x[lane] = x[lane] * sc[2];
+    if (lane == 0) x[0] = from_real<T>(1.0);
     __syncthreads();
 }
 
+// One wave per workgroup; lane i owns row i of the b x b blocks, so the
+// matrix-vector products and rank-1 updates need no cross-lane reduction
+// and the only barriers are where a lane reads another lane's row.  E and D
+// live in dynamic LDS, (b x (b+1)) each.
 template <typename T>
-__global__ __launch_bounds__(HT) void hb2st_kernel(int n, int b, T* Bw, long ldw, T* V2, T* tau2, int nsw,
-                                                   int* progress, int* counter, int* hang) {
-    __shared__ T E[MAXB][MAXB + 1];
-    __shared__ T D[MAXB][MAXB + 1];
-    __shared__ T v[MAXB], vp[MAXB], y[MAXB], red[4][MAXB];
+__global__ __launch_bounds__(64) void hb2st_kernel(int n, int b, T* Bw, long ldw, T* V2, T* tau2, int nsw,
+                                                  int* progress, int* counter, int* hang) {
+    extern __shared__ char lds_raw[];
+    T* Eb = reinterpret_cast<T*>(lds_raw);
+    T* Db = Eb + (size_t)b * (b + 1);
+    const int ldl = b + 1;
+    __shared__ T v[MAXB], vp[MAXB], y[MAXB];
     __shared__ T sc[4];
     __shared__ T ptau;
     __shared__ int sw_s, stop;
-    const int tid = threadIdx.x;
+    const int lane = threadIdx.x;
+#define EL_(i, j) Eb[(i) * ldl + (j)]
+#define DL_(i, j) Db[(i) * ldl + (j)]
 
     for (;;) {
-        if (tid == 0) {
+        if (lane == 0) {
             sw_s = atomicAdd(counter, 1);
             stop = 0;
         }
@@ -108,96 +87,100 @@ __global__ __launch_bounds__(HT) void hb2st_kernel(int n, int b, T* Bw, long ldw
         const int nt = ntasks(n, b, sw);
         for (int t = 0; t < nt; ++t) {
             if (sw > 0) {
-                if (tid == 0) {
+                if (lane == 0) {
                     const int need = min(t + 2, ntasks(n, b, sw - 1));
                     long long spins = 0;
-                    while (__hip_atomic_load(&progress[sw - 1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < need) {
+                    // relaxed polling; one acquire fence once it is satisfied
+                    while (__hip_atomic_load(&progress[sw - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
                         if (++spins > SPIN_LIMIT ||
                             __hip_atomic_load(hang, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
                             atomicOr(hang, 1);
                             stop = 1;
                             break;
                         }
-                        __builtin_amdgcn_s_sleep(2);
+                        __builtin_amdgcn_s_sleep(1);
                     }
                 }
                 __syncthreads();
                 if (stop) return;
-                __threadfence();  // acquire for every wave before reading the band
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             }
             const int r0 = sw + 1 + t * b;
             const int L = min(b, n - r0);
             if (t == 0) {
-                // column sw, rows r0 .. r0+L-1 (band rows 1 .. L)
-                if (tid < L) v[tid] = Bw[IDX(1 + tid, sw, ldw)];
+                if (lane < L) v[lane] = Bw[IDX(1 + lane, sw, ldw)];
                 __syncthreads();
-                reflect<T>(v, L, sc);
-                if (tid < L) Bw[IDX(1 + tid, sw, ldw)] = (tid == 0) ? sc[1] : zero_of<T>();
+                reflect1<T>(v, L, sc);
+                if (lane < L) Bw[IDX(1 + lane, sw, ldw)] = (lane == 0) ? sc[1] : zero_of<T>();
             } else {
                 const int pr0 = r0 - b;  // previous block (always b rows)
-                for (int e = tid; e < L * b; e += HT) {
-                    const int i = e % L, j = e / L;
-                    E[i][j] = Bw[IDX(b + i - j, pr0 + j, ldw)];
-                }
-                __syncthreads();
-                // E <- E (I - ptau vp vp^H)
-                dot_rows<T>(E, vp, y, red, L, b);
                 const T pt = ptau;
-                for (int e = tid; e < L * b; e += HT) {
-                    const int i = e % L, j = e / L;
-                    E[i][j] -= pt * y[i] * conjg(vp[j]);
+                if (lane < L) {
+                    const int i = lane;
+                    T acc = zero_of<T>();
+                    for (int j = 0; j < b; ++j) {
+                        const T x = Bw[IDX(b + i - j, pr0 + j, ldw)];
+                        EL_(i, j) = x;
+                        acc += x * vp[j];
+                    }
+                    // row i of E (I - ptau vp vp^H)
+                    const T pa = pt * acc;
+                    for (int j = 0; j < b; ++j) EL_(i, j) -= pa * conjg(vp[j]);
+                    v[i] = EL_(i, 0);
                 }
                 __syncthreads();
                 if (L >= 2) {
-                    if (tid < L) v[tid] = E[tid][0];
-                    __syncthreads();
-                    reflect<T>(v, L, sc);
-                    // E[:, 1:] <- (I - tau v v^H)^H E[:, 1:]
-                    dot_cols<T>(E, v, y, red, L, b);
-                    const T ctau = conjg(sc[0]);
-                    for (int e = tid; e < L * b; e += HT) {
-                        const int i = e % L, j = e / L;
-                        if (j >= 1) E[i][j] -= ctau * v[i] * y[j];
-                        else E[i][0] = (i == 0) ? sc[1] : zero_of<T>();
+                    reflect1<T>(v, L, sc);
+                    // y_j = v^H E[:, j] (lane j), then E[:, 1:] -= conj(tau) v y^H
+                    if (lane < b) {
+                        T acc = zero_of<T>();
+                        for (int i = 0; i < L; ++i) acc += conjg(v[i]) * EL_(i, lane);
+                        y[lane] = acc;
                     }
                     __syncthreads();
+                    const T ctau = conjg(sc[0]);
+                    if (lane < L) {
+                        const int i = lane;
+                        const T cv = ctau * v[i];
+                        for (int j = 1; j < b; ++j) Bw[IDX(b + i - j, pr0 + j, ldw)] = EL_(i, j) - cv * y[j];
+                        Bw[IDX(b + i, pr0, ldw)] = (i == 0) ? sc[1] : zero_of<T>();
+                    }
                 } else {
-                    if (tid == 0) {
+                    if (lane == 0) {
                         v[0] = from_real<T>(1.0);
                         sc[0] = zero_of<T>();
                     }
+                    if (lane < L)
+                        for (int j = 0; j < b; ++j) Bw[IDX(b + lane - j, pr0 + j, ldw)] = EL_(lane, j);
                     __syncthreads();
-                }
-                for (int e = tid; e < L * b; e += HT) {
-                    const int i = e % L, j = e / L;
-                    Bw[IDX(b + i - j, pr0 + j, ldw)] = E[i][j];
                 }
             }
             // two-sided update of the diagonal block rows/cols r0 .. r0+L-1
             const T tau = sc[0];
-            for (int e = tid; e < L * L; e += HT) {
-                const int i = e % L, j = e / L;
-                if (i >= j) {
-                    const T x = Bw[IDX(i - j, r0 + j, ldw)];
-                    D[i][j] = x;
-                    D[j][i] = conjg(x);
-                }
-            }
-            __syncthreads();
             if (!is_zero(tau)) {
-                dot_rows<T>(D, v, y, red, L, L);  // y = D v
-                if (tid < WAVE) {
-                    T yi = (tid < L) ? tau * y[tid] : zero_of<T>();
-                    T s = (tid < L) ? conjg(yi) * v[tid] : zero_of<T>();
-                    s = wave_sum(s);
-                    const T coef = from_real<T>(-0.5) * tau * s;  // -1/2 tau (y^H v)
-                    if (tid < L) y[tid] = yi + coef * v[tid];     // w
+                if (lane < L) {
+                    const int i = lane;
+                    for (int j = 0; j <= i; ++j) {
+                        const T x = Bw[IDX(i - j, r0 + j, ldw)];
+                        DL_(i, j) = x;
+                        DL_(j, i) = conjg(x);
+                    }
                 }
                 __syncthreads();
-                for (int e = tid; e < L * L; e += HT) {
-                    const int i = e % L, j = e / L;
-                    if (i >= j) {
-                        T x = D[i][j] - v[i] * conjg(y[j]) - y[i] * conjg(v[j]);
+                if (lane < L) {
+                    T acc = zero_of<T>();
+                    for (int j = 0; j < L; ++j) acc += DL_(lane, j) * v[j];
+                    y[lane] = tau * acc;
+                }
+                T yv = (lane < L) ? conjg(y[lane]) * v[lane] : zero_of<T>();
+                yv = wave_sum(yv);
+                const T coef = from_real<T>(-0.5) * tau * yv;  // w = y - 1/2 tau (y^H v) v
+                if (lane < L) y[lane] = y[lane] + coef * v[lane];
+                __syncthreads();
+                if (lane < L) {
+                    const int i = lane;
+                    for (int j = 0; j <= i; ++j) {
+                        T x = DL_(i, j) - v[i] * conjg(y[j]) - y[i] * conjg(v[j]);
                         if (i == j) x = from_real<T>(realp(x));
                         Bw[IDX(i - j, r0 + j, ldw)] = x;
                     }
@@ -205,17 +188,19 @@ __global__ __launch_bounds__(HT) void hb2st_kernel(int n, int b, T* Bw, long ldw
             }
             // keep the reflector for the back-transformation and the next task
             const size_t slot = (size_t)t * nsw + sw;
-            if (tid < b) V2[slot * b + tid] = (tid < L) ? v[tid] : zero_of<T>();
-            if (tid == 0) tau2[slot] = tau;
+            if (lane < b) V2[slot * b + lane] = (lane < L) ? v[lane] : zero_of<T>();
+            if (lane == 0) tau2[slot] = tau;
             __syncthreads();
-            if (tid < MAXB) vp[tid] = (tid < L) ? v[tid] : zero_of<T>();
-            if (tid == 0) ptau = tau;
-            __threadfence();  // every wave's band stores visible device-wide
+            if (lane < MAXB) vp[lane] = (lane < L) ? v[lane] : zero_of<T>();
+            if (lane == 0) ptau = tau;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // this wave's band stores, device-wide
             __syncthreads();
-            if (tid == 0)
+            if (lane == 0)
                 __hip_atomic_store(&progress[sw], t + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
+#undef EL_
+#undef DL_
 }
 
 template <typename T>
@@ -230,69 +215,220 @@ __global__ void extract_tridiag(int n, const T* Bw, long ldw, double* d, double*
 // Back-transformation Z <- Q2 Z.  Q2 = prod over sweeps (ascending) of prod
 // over blocks (ascending) of H(s, t).  Reflectors of one sweep touch disjoint
 // rows; H(s', t-1) and H(s', t) with s' > s must precede H(s, t).  Sweeps are
-// grouped in blocks of NBS <= b; blocks are applied last-first, within a
-// block the groups G(S, t) in t order, inside a group the sweeps last-first.
-// A workgroup owns CT columns of Z and keeps the rows of the current group
-// in an LDS window indexed modulo 2b (a group spans at most 2b-1 rows and
-// consecutive groups slide by b).  Each wave owns CT/4 columns, so a
-// reflector costs only wave-level reductions, no workgroup barrier.
+// grouped in blocks of NBS; blocks are applied last-first and within a block
+// the groups G(S, t) in t order.  A group's product H(s0,t)...H(s0+NBS-1,t)
+// is I - V T V^H with V the NBS reflectors as a staircase (reflector j starts
+// j rows below the group's first row, so the group spans NBS+b-1 rows), and
+// is applied to the window of Z rows as three small products on the MFMA
+// units: W = V^H Z, W <- T W, Z <- Z - V W.  The T factors of all groups are
+// formed beforehand, in parallel (forward accumulation from the Gram matrix
+// V^H V).  A workgroup owns 16 columns of Z and keeps the group's rows in an
+// LDS ring of 128 rows (a group spans at most 127 rows; consecutive groups
+// slide by b).
 // ---------------------------------------------------------------------------
-template <typename T, int CT>
-__global__ __launch_bounds__(256) void back_chase_kernel(int n, int b, int nsw, int nbs, const T* V2, const T* tau2,
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+template <typename T, int NBS>
+__global__ __launch_bounds__(256) void chase_tfactor_kernel(int n, int b, int nsw, int nblk, const T* V2,
+                                                            const T* tau2, T* Tg) {
+    constexpr int NC = is_cplx<T>::value ? 2 : 1;
+    __shared__ T vc[NBS][MAXB];
+    __shared__ T G[NBS][NBS + 1];
+    __shared__ T Tm[NBS][NBS + 1];
+    __shared__ T tau[NBS];
+    (void)NC;
+    const int S = blockIdx.x, t = blockIdx.y, tid = threadIdx.x;
+    const int s0 = S * NBS;
+    for (int e = tid; e < NBS * b; e += 256) {
+        const int j = e / b, q = e % b, s = s0 + j;
+        const bool ok = s < nsw && s + 1 + t * b < n;
+        vc[j][q] = ok ? V2[((size_t)t * nsw + s) * b + q] : zero_of<T>();
+    }
+    if (tid < NBS) {
+        const int s = s0 + tid;
+        const bool ok = s < nsw && s + 1 + t * b < n;
+        tau[tid] = ok ? tau2[(size_t)t * nsw + s] : zero_of<T>();
+    }
+    __syncthreads();
+    // Gram G[i][j] = v_i^H v_j over the overlap of their row ranges (i < j)
+    for (int e = tid; e < NBS * NBS; e += 256) {
+        const int i = e % NBS, j = e / NBS;
+        T acc = zero_of<T>();
+        if (i < j && j - i < b)
+            for (int q = 0; q + (j - i) < b; ++q) acc += conjg(vc[i][q + (j - i)]) * vc[j][q];
+        G[i][j] = acc;
+    }
+    __syncthreads();
+    // T[j][j] = tau_j, T[0:j, j] = -tau_j T[0:j, 0:j] G[0:j, j]
+    for (int j = 0; j < NBS; ++j) {
+        if (tid < j) {
+            T acc = zero_of<T>();
+            for (int l = tid; l < j; ++l) acc += Tm[tid][l] * G[l][j];
+            Tm[tid][j] = -(tau[j] * acc);
+        } else if (tid == j) {
+            Tm[j][j] = tau[j];
+        } else if (tid < NBS) {
+            Tm[tid][j] = zero_of<T>();
+        }
+        __syncthreads();
+    }
+    T* out = Tg + ((size_t)t * nblk + S) * NBS * NBS;
+    for (int e = tid; e < NBS * NBS; e += 256) out[e] = Tm[e / NBS][e % NBS];  // row-major
+}
+
+template <typename T>
+__device__ inline void mma4(dbl4& cr, dbl4& ci, double ar, double ai, double br, double bi) {
+    cr = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, br, cr, 0, 0, 0);
+    if constexpr (is_cplx<T>::value) {
+        cr = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai, bi, cr, 0, 0, 0);
+        ci = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, bi, ci, 0, 0, 0);
+        ci = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, br, ci, 0, 0, 0);
+    }
+}
+
+template <typename T, int NBS>
+__global__ __launch_bounds__(256) void back_chase_kernel(int n, int b, int nsw, int nblk, const T* V2, const T* Tg,
                                                          int nev, T* Z, long ldz) {
-    __shared__ T win[2 * MAXB][CT];
+    constexpr int CX = is_cplx<T>::value ? 1 : 0;
+    constexpr int NC = CX + 1;
+    constexpr int CT = 16, RING = 2 * MAXB;
+    constexpr int NB1 = NBS / 16, P = 4 / NB1;
+    __shared__ double vc[NC][NBS][MAXB];   // reflector j, entry q
+    __shared__ double tm[NC][NBS][NBS];    // T row-major
+    __shared__ double zr[NC][RING][CT];    // Z rows, ring-indexed by absolute row
+    __shared__ double wp[NC][P][NBS][CT];  // partial V^H Z
+    __shared__ double w1[NC][NBS][CT];     // V^H Z, then T V^H Z
     const int tid = threadIdx.x, lane = tid % WAVE, wv = tid / WAVE;
     const int c0 = blockIdx.x * CT;
     const int ncol = min(CT, nev - c0);
-    const int W2 = 2 * b;
-    constexpr int CPW = CT / 4;  // columns per wave
-    const int nblk = (nsw + nbs - 1) / nbs;
+    const int li = lane % 16, lk = lane / 16;
 
-    auto load_rows = [&](int ra, int rb) {  // rows [ra, rb) of Z into the window
+    auto load_rows = [&](int ra, int rb) {
         const int nr = rb - ra;
         for (int e = tid; e < nr * CT; e += 256) {
             const int r = ra + e % nr, c = e / nr;
-            win[r % W2][c] = (c < ncol) ? Z[IDX(r, c0 + c, ldz)] : zero_of<T>();
+            const T v = (c < ncol) ? Z[IDX(r, c0 + c, ldz)] : zero_of<T>();
+            zr[0][r & (RING - 1)][c] = realp(v);
+            if (CX) zr[NC - 1][r & (RING - 1)][c] = imagp(v);
         }
     };
     auto store_rows = [&](int ra, int rb) {
         const int nr = rb - ra;
         for (int e = tid; e < nr * CT; e += 256) {
             const int r = ra + e % nr, c = e / nr;
-            if (c < ncol) Z[IDX(r, c0 + c, ldz)] = win[r % W2][c];
+            if (c < ncol) {
+                T v;
+                if constexpr (CX) v = zdouble{zr[0][r & (RING - 1)][c], zr[NC - 1][r & (RING - 1)][c]};
+                else v = zr[0][r & (RING - 1)][c];
+                Z[IDX(r, c0 + c, ldz)] = v;
+            }
         }
+    };
+    // V[r][j] of the current group (r relative to the window start)
+    auto vget = [&](int comp, int r, int j, int lg) -> double {
+        const int q = r - j;
+        return (r < lg && q >= 0 && q < b) ? vc[comp][j][q] : 0.0;
     };
 
     for (int S = nblk - 1; S >= 0; --S) {
-        const int s0 = S * nbs, s1 = min(nsw, s0 + nbs);
-        int lo = -1, hi = -1;  // rows currently held in the window
+        const int s0 = S * NBS, s1 = min(nsw, s0 + NBS);
+        int lo = -1, hi = -1;
         for (int t = 0;; ++t) {
             const int wr0 = s0 + 1 + t * b;
             if (wr0 >= n) break;
-            const int wr1 = min(n, (s1 - 1) + 1 + t * b + b);
-            // write back rows leaving the window, load rows entering it
+            const int wr1 = min(n, s1 + t * b + b);
+            const int lg = wr1 - wr0;
             if (hi > lo) store_rows(lo, min(hi, wr0));
             const int la = (hi > wr0) ? hi : wr0;
             __syncthreads();
             if (wr1 > la) load_rows(la, wr1);
             lo = wr0;
             hi = wr1;
+            // group reflectors and T
+            // reflector slots past the end of the matrix were never written
+            const T* vsrc = V2 + ((size_t)t * nsw + s0) * b;
+            for (int e = tid; e < NBS * b; e += 256) {
+                const int j = e / b, q = e % b, s = s0 + j;
+                const bool ok = s < s1 && s + 1 + t * b < n;
+                const T v = ok ? vsrc[e] : zero_of<T>();
+                vc[0][j][q] = realp(v);
+                if (CX) vc[NC - 1][j][q] = imagp(v);
+            }
+            const T* tsrc = Tg + ((size_t)t * nblk + S) * NBS * NBS;
+            for (int e = tid; e < NBS * NBS; e += 256) {
+                const T v = tsrc[e];
+                tm[0][e / NBS][e % NBS] = realp(v);
+                if (CX) tm[NC - 1][e / NBS][e % NBS] = imagp(v);
+            }
             __syncthreads();
-            for (int s = s1 - 1; s >= s0; --s) {
-                const int r0 = s + 1 + t * b;
-                if (r0 >= n) continue;
-                const int L = min(b, n - r0);
-                const size_t slot = (size_t)t * nsw + s;
-                const T tau = tau2[slot];
-                if (is_zero(tau)) continue;
-                const T vi = (lane < L) ? V2[slot * b + lane] : zero_of<T>();
-                const T cvi = conjg(vi);
+            const int base = wr0;
+            // ---- W = V^H Z: block jb of NBS/16, inner range split in P parts
+            {
+                const int jb = wv % NB1, part = wv / NB1;
+                const int k0 = jb * 16, k1 = min(lg, jb * 16 + 15 + b);
+                const int len = max(k1 - k0, 0);
+                const int chunk = ((len + P - 1) / P + 3) / 4 * 4;
+                const int ka = k0 + part * chunk, kb = min(k1, ka + chunk);
+                dbl4 cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
+                for (int k = ka; k < kb; k += 4) {
+                    const int r = k + lk, j = jb * 16 + li;
+                    const double ar = vget(0, r, j, lg), ai = CX ? -vget(NC - 1, r, j, lg) : 0.0;  // conj(V)
+                    const bool in = r < kb;
+                    const double br = in ? zr[0][(base + r) & (RING - 1)][li] : 0.0;
+                    const double bi = (CX && in) ? zr[NC - 1][(base + r) & (RING - 1)][li] : 0.0;
+                    mma4<T>(cr, ci, in ? ar : 0.0, in ? ai : 0.0, br, bi);
+                }
 #pragma unroll
-                for (int q = 0; q < CPW; ++q) {
-                    const int c = wv * CPW + q;
-                    T z = (lane < L) ? win[(r0 + lane) % W2][c] : zero_of<T>();
-                    T dot = wave_sum(cvi * z);
-                    if (lane < L) win[(r0 + lane) % W2][c] = z - tau * vi * dot;
+                for (int rr = 0; rr < 4; ++rr) {
+                    wp[0][part][jb * 16 + 4 * rr + lk][li] = cr[rr];
+                    if (CX) wp[NC - 1][part][jb * 16 + 4 * rr + lk][li] = ci[rr];
+                }
+            }
+            __syncthreads();
+            for (int e = tid; e < NBS * CT; e += 256) {
+                const int j = e / CT, c = e % CT;
+#pragma unroll
+                for (int comp = 0; comp < NC; ++comp) {
+                    double acc = wp[comp][0][j][c];
+                    for (int q = 1; q < P; ++q) acc += wp[comp][q][j][c];
+                    wp[comp][0][j][c] = acc;
+                }
+            }
+            __syncthreads();
+            // ---- W1 = T W (T upper triangular)
+            if (wv < NB1) {
+                const int jb = wv;
+                dbl4 cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
+                for (int k = jb * 16; k < NBS; k += 4) {
+                    const double ar = tm[0][jb * 16 + li][k + lk], ai = CX ? tm[NC - 1][jb * 16 + li][k + lk] : 0.0;
+                    const double br = wp[0][0][k + lk][li], bi = CX ? wp[NC - 1][0][k + lk][li] : 0.0;
+                    mma4<T>(cr, ci, ar, ai, br, bi);
+                }
+#pragma unroll
+                for (int rr = 0; rr < 4; ++rr) {
+                    w1[0][jb * 16 + 4 * rr + lk][li] = cr[rr];
+                    if (CX) w1[NC - 1][jb * 16 + 4 * rr + lk][li] = ci[rr];
+                }
+            }
+            __syncthreads();
+            // ---- Z <- Z - V W1, row blocks of 16 over the window
+            const int nrb = (lg + 15) / 16;
+            for (int rb = wv; rb < nrb; rb += 4) {
+                const int ka = max(0, rb * 16 - b + 1) / 4 * 4, kb = min(NBS, rb * 16 + 16);
+                dbl4 cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
+                for (int k = ka; k < kb; k += 4) {
+                    const int r = rb * 16 + li, j = k + lk;
+                    const double ar = vget(0, r, j, lg), ai = CX ? vget(NC - 1, r, j, lg) : 0.0;
+                    const double br = w1[0][j][li], bi = CX ? w1[NC - 1][j][li] : 0.0;
+                    mma4<T>(cr, ci, ar, ai, br, bi);
+                }
+#pragma unroll
+                for (int rr = 0; rr < 4; ++rr) {
+                    const int r = rb * 16 + 4 * rr + lk;
+                    if (r < lg) {
+                        zr[0][(base + r) & (RING - 1)][li] -= cr[rr];
+                        if (CX) zr[NC - 1][(base + r) & (RING - 1)][li] -= ci[rr];
+                    }
                 }
             }
             __syncthreads();
@@ -318,8 +454,11 @@ int hb2st(const StageCtx& c, int n, T* Bw, long ldw, ChaseRefl<T>& R, double* d,
             return rc;
         int* progress = sync_area;
         int* counter = sync_area + R.nsw + 1;
-        const int grid = std::min(R.nsw, 240);
-        hipLaunchKernelGGL(hb2st_kernel<T>, dim3(grid), dim3(HT), 0, st, n, b, Bw, ldw, R.V2, R.tau2, R.nsw, progress,
+        const int grid = std::min(R.nsw, 1024);
+        const size_t lds = (size_t)2 * b * (b + 1) * sizeof(T);
+        GEVD_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&hb2st_kernel<T>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        hipLaunchKernelGGL(hb2st_kernel<T>, dim3(grid), dim3(64), lds, st, n, b, Bw, ldw, R.V2, R.tau2, R.nsw, progress,
                            counter, c.hang);
         GEVD_LAUNCH_CHECK();
     }
@@ -331,11 +470,14 @@ int hb2st(const StageCtx& c, int n, T* Bw, long ldw, ChaseRefl<T>& R, double* d,
 template <typename T>
 int back_chase(const StageCtx& c, const ChaseRefl<T>& R, int nev, T* Z, long ldz) {
     if (R.nsw <= 0 || nev <= 0) return 0;
-    constexpr int CT = is_cplx<T>::value ? 8 : 16;
-    const int grid = (nev + CT - 1) / CT;
-    const int nbs = R.b;  // sweeps per block (<= b keeps a group within 2b-1 rows)
-    hipLaunchKernelGGL((back_chase_kernel<T, CT>), dim3(grid), dim3(256), 0, c.st, R.n, R.b, R.nsw, nbs,
-                       (const T*)R.V2, (const T*)R.tau2, nev, Z, ldz);
+    constexpr int NBS = chase_group<T>();
+    if (R.nbs != NBS || R.Tg == nullptr || R.b > MAXB) return GEVD_E_STATE;
+    hipLaunchKernelGGL((chase_tfactor_kernel<T, NBS>), dim3(R.nblk, R.tmax), dim3(256), 0, c.st, R.n, R.b, R.nsw,
+                       R.nblk, (const T*)R.V2, (const T*)R.tau2, R.Tg);
+    GEVD_LAUNCH_CHECK();
+    const int grid = (nev + 15) / 16;
+    hipLaunchKernelGGL((back_chase_kernel<T, NBS>), dim3(grid), dim3(256), 0, c.st, R.n, R.b, R.nsw, R.nblk,
+                       (const T*)R.V2, (const T*)R.Tg, nev, Z, ldz);
     GEVD_LAUNCH_CHECK();
     return 0;
 }

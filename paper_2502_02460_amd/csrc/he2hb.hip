@@ -7,8 +7,8 @@
 // H_s = I - tau_s v_s v_s^H (beta real), then the trailing m x m block is
 // updated two-sidedly with the compact WY form Q = I - V T V^H:
 //   X = A22 V T,  W = X - 1/2 V (T^H V^H X),  A22 <- A22 - W V^H - V W^H,
-// all as MFMA products.  The panel QR is latency-bound: each column costs two
-// row-parallel launches whose reductions finish in the last workgroup to
+// all as MFMA products.  The panel QR is latency-bound: each column costs one
+// row-parallel launch whose reductions finish in the last workgroup to
 // arrive (fixed summation order, so results are deterministic).
 #include "stages.hpp"
 
@@ -43,90 +43,83 @@ __device__ inline void make_reflector(T alpha, double xn2, T* tau, T* scale, dou
     *beta = bt;
 }
 
-// Column s of the panel: v_s (into Vp, with v[s] = 1 and zeros above), the
-// products w_j = v_s^H P[:, j] for j > s, and P[s, s] = beta_s.
+// One launch per panel column s (0 <= s <= nref), rows split across
+// workgroups:
+//  1. if s > 0, apply reflector s-1 to this workgroup's rows of columns
+//     j >= s: P[i, j] -= conj(tau) v_i w_j, with v_i = P[i, s-1] * scale
+//     (v[s-1] = 1), and store v into Vp[:, s-1];
+//  2. if s < nref, partial sums of |P[i, s]|^2 (i > s) and of
+//     y_j = sum_{i > s} conj(P[i, s]) P[i, j] (j > s).  The last workgroup
+//     to finish adds the partials in workgroup order, forms reflector s
+//     (beta, tau, scale = 1/(alpha - beta)) and w_j = v_s^H P[:, j] =
+//     conj(scale) y_j + P[s, j], which needs no second pass over the rows.
 template <typename T>
-__global__ __launch_bounds__(PT) void panel_apply(T* P, long lda, int m, int b, int s, T* Vp,
-                                                  PanelScratch<T>* ps, T* partial) {
-    __shared__ T red[PT / WAVE][MAXB];
+__global__ __launch_bounds__(PT) void panel_step(T* P, long lda, int m, int b, int s, int nref, T* Vp,
+                                                 PanelScratch<T>* ps, T* partial) {
+    __shared__ T red[PT / WAVE][MAXB + 1];
     __shared__ int last;
-    const int tid = threadIdx.x;
-    const int r = s + blockIdx.x * PT + tid;
-    const T scale = ps->scale;
-    T v = zero_of<T>();
-    if (r < m) {
-        v = (r == s) ? from_real<T>(1.0) : P[IDX(r, s, lda)] * scale;
-        Vp[IDX(r, s, m)] = v;
+    const int tid = threadIdx.x, w = tid / WAVE, l = tid % WAVE;
+    const int r0 = s > 0 ? s - 1 : 0;
+    const int r = r0 + blockIdx.x * PT + tid;
+    if (s > 0) {
+        const int sp = s - 1;
+        if (r < m) {
+            const T v = (r == sp) ? from_real<T>(1.0) : P[IDX(r, sp, lda)] * ps->scale;
+            Vp[IDX(r, sp, m)] = v;
+            const T ctv = conjg(ps->tau[sp]) * v;
+            for (int j = s; j < b; ++j) P[IDX(r, j, lda)] -= ctv * ps->w[j];
+        }
+        if (blockIdx.x == 0)
+            for (int i = tid; i < sp; i += PT) Vp[IDX(i, sp, m)] = zero_of<T>();
     }
-    if (blockIdx.x == 0)
-        for (int i = tid; i < s; i += PT) Vp[IDX(i, s, m)] = zero_of<T>();
-    const int w = tid / WAVE, l = tid % WAVE;
-    const T cv = conjg(v);
+    if (s >= nref) return;
+    const bool below = r > s && r < m;
+    const T x = below ? P[IDX(r, s, lda)] : zero_of<T>();
+    double nx = wave_sum(abs2(x));
+    if (l == 0) red[w][MAXB] = from_real<T>(nx);
+    const T cx = conjg(x);
     for (int j = s + 1; j < b; ++j) {
-        T x = (r < m) ? cv * P[IDX(r, j, lda)] : zero_of<T>();
-        x = wave_sum(x);
-        if (l == 0) red[w][j] = x;
+        T y = below ? cx * P[IDX(r, j, lda)] : zero_of<T>();
+        y = wave_sum(y);
+        if (l == 0) red[w][j] = y;
     }
     __syncthreads();
-    if (tid > s && tid < b) {
+    T* part = partial + (size_t)blockIdx.x * (MAXB + 1);
+    if ((tid > s && tid < b) || tid == MAXB) {
         T acc = red[0][tid];
         for (int q = 1; q < PT / WAVE; ++q) acc += red[q][tid];
-        partial[(size_t)blockIdx.x * b + tid] = acc;
+        part[tid] = acc;
     }
-    __threadfence();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
     if (tid == 0) last = (atomicAdd(&ps->counter, 1u) == gridDim.x - 1);
     __syncthreads();
     if (!last) return;
-    __threadfence();
-    if (tid > s && tid < b) {
-        T acc = zero_of<T>();
-        for (unsigned g = 0; g < gridDim.x; ++g) acc += partial[(size_t)g * b + tid];
-        ps->w[tid] = acc;
-    }
-    if (tid == 0) {
-        ps->counter = 0;
-        P[IDX(s, s, lda)] = from_real<T>(ps->beta);
-    }
-}
-
-// Rank-1 update of the columns right of s with reflector s (if s >= 0),
-// then the norm of column s+1 below its diagonal and reflector s+1 (if
-// s+1 < nref), finished by the last workgroup.
-template <typename T>
-__global__ __launch_bounds__(PT) void panel_update(T* P, long lda, int m, int b, int s, int nref, const T* Vp,
-                                                   PanelScratch<T>* ps, double* partial) {
-    __shared__ double red[PT / WAVE];
-    __shared__ int last;
-    const int tid = threadIdx.x;
-    const int r0 = s < 0 ? 0 : s;
-    const int r = r0 + blockIdx.x * PT + tid;
-    const int nx = s + 1;
-    if (s >= 0 && r < m) {
-        const T ctv = conjg(ps->tau[s]) * Vp[IDX(r, s, m)];
-        for (int j = s + 1; j < b; ++j) P[IDX(r, j, lda)] -= ctv * ps->w[j];
-    }
-    if (nx >= nref) return;
-    double x = (r > nx && r < m) ? abs2(P[IDX(r, nx, lda)]) : 0.0;
-    x = block_sum<PT>(x, red);
-    if (tid == 0) partial[blockIdx.x] = x;
-    __threadfence();
-    __syncthreads();
-    if (tid == 0) last = (atomicAdd(&ps->counter, 1u) == gridDim.x - 1);
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    __shared__ T fin[3];  // tau, scale
+    __shared__ double bt;
     if (tid == 0) {
         double xn2 = 0.0;
-        for (unsigned g = 0; g < gridDim.x; ++g) xn2 += partial[g];
+        for (unsigned g = 0; g < gridDim.x; ++g) xn2 += realp(partial[(size_t)g * (MAXB + 1) + MAXB]);
         T tau, scale;
         double beta;
-        make_reflector<T>(P[IDX(nx, nx, lda)], xn2, &tau, &scale, &beta);
-        ps->tau[nx] = tau;
+        make_reflector<T>(P[IDX(s, s, lda)], xn2, &tau, &scale, &beta);
+        fin[0] = tau;
+        fin[1] = scale;
+        bt = beta;
+        ps->tau[s] = tau;
         ps->scale = scale;
         ps->beta = beta;
         ps->counter = 0;
     }
+    __syncthreads();
+    if (tid > s && tid < b) {
+        T acc = zero_of<T>();
+        for (unsigned g = 0; g < gridDim.x; ++g) acc += partial[(size_t)g * (MAXB + 1) + tid];
+        ps->w[tid] = conjg(fin[1]) * acc + P[IDX(s, tid, lda)];
+    }
+    __syncthreads();
+    if (tid == 0) P[IDX(s, s, lda)] = from_real<T>(bt);
 }
 
 // T (b x b upper) of Q = H_0 ... H_{b-1} = I - V T V^H from the Gram matrix
@@ -210,7 +203,7 @@ size_t carve_ws(char* base, int n, int b, He2hbWs<T>* w) {
     t.M2 = c.take<T>((size_t)b * b);
     t.skS = c.take<T>((size_t)SK * b * b);
     const size_t nwg = (size_t)(n + PT - 1) / PT + 1;
-    t.partialT = c.take<T>(nwg * b);
+    t.partialT = c.take<T>(nwg * (MAXB + 1));
     t.partialD = c.take<double>(nwg);
     t.ps = c.take<PanelScratch<T>>(1);
     if (w) *w = t;
@@ -247,17 +240,10 @@ int he2hb(const StageCtx& c, int n, T* A, long lda, BandRefl<T>& R, T* Bd, long 
         T* Vp = R.V + R.voff(p);
         T* Tp = R.Tf + (size_t)p * b * b;
         if ((rc = set_zero<T>(st, m, b, Vp, m))) return rc;
-        // reflector 0
-        hipLaunchKernelGGL(panel_update<T>, dim3((m + PT - 1) / PT), dim3(PT), 0, st, P, lda, m, b, -1, nref,
-                           (const T*)Vp, w.ps, w.partialD);
-        GEVD_LAUNCH_CHECK();
-        for (int s = 0; s < nref; ++s) {
-            const int rows = m - s;
-            const unsigned g = (unsigned)((rows + PT - 1) / PT);
-            hipLaunchKernelGGL(panel_apply<T>, dim3(g), dim3(PT), 0, st, P, lda, m, b, s, Vp, w.ps, w.partialT);
-            GEVD_LAUNCH_CHECK();
-            hipLaunchKernelGGL(panel_update<T>, dim3(g), dim3(PT), 0, st, P, lda, m, b, s, nref, (const T*)Vp, w.ps,
-                               w.partialD);
+        for (int s = 0; s <= nref; ++s) {
+            const int r0 = s > 0 ? s - 1 : 0;
+            const unsigned g = (unsigned)((m - r0 + PT - 1) / PT);
+            hipLaunchKernelGGL(panel_step<T>, dim3(g), dim3(PT), 0, st, P, lda, m, b, s, nref, Vp, w.ps, w.partialT);
             GEVD_LAUNCH_CHECK();
         }
         // T factor from G = V^H V

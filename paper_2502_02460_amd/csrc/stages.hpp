@@ -36,7 +36,16 @@ struct ChaseRefl {
     int n = 0, b = 0, nsw = 0, tmax = 0;
     T* V2 = nullptr;
     T* tau2 = nullptr;
+    // back-transformation groups: nbs consecutive sweeps at one block index t,
+    // group (S, t) has compact-WY factor T at Tg + (t*nblk + S)*nbs*nbs
+    int nbs = 0, nblk = 0;
+    T* Tg = nullptr;
 };
+// sweeps per back-transformation group
+template <typename T>
+constexpr int chase_group() {
+    return is_cplx<T>::value ? 32 : 64;
+}
 
 template <typename T>
 size_t band_ws_bytes(int n, int b);

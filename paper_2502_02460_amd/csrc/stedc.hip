@@ -295,6 +295,13 @@ __device__ inline double secular(const double* delta, const double* zc, int kn, 
     return f;
 }
 
+// Root j of 1 + rho sum_i z_i^2/(delta_i - lam), lam = delta[o] + tau with o
+// the nearer pole.  Each iteration evaluates the poles left of the interval
+// (psi) and right of it (phi) with their derivatives, replaces them by one
+// pole each with matching value and slope (a two-pole rational model; for
+// the last root one pole), and steps to the model's root in the interval.
+// The sign of f keeps a bracket; a model step that leaves it is replaced by
+// bisection, so convergence never depends on the model.
 __global__ void merge_secular_kernel(const double* e, const MergeDesc* md, const double* delta_all,
                                      const double* zc_all, int* org, double* tauv, double* lam) {
     const MergeDesc M = md[blockIdx.y];
@@ -304,9 +311,10 @@ __global__ void merge_secular_kernel(const double* e, const MergeDesc* md, const
     const double rho = 2.0 * fabs(e[off + M.n1 - 1]);
     const double* delta = delta_all + off;
     const double* zc = zc_all + off;
+    const bool last = j == kn - 1;
     int o;
     double lo, hi;
-    if (j < kn - 1) {
+    if (!last) {
         const double gap = delta[j + 1] - delta[j];
         const double fm = secular(delta, zc, kn, rho, delta[j], 0.5 * gap);
         if (fm >= 0.0) {
@@ -327,16 +335,68 @@ __global__ void merge_secular_kernel(const double* e, const MergeDesc* md, const
         for (int g = 0; g < 64 && secular(delta, zc, kn, rho, delta[o], hi) < 0.0; ++g) hi *= 2.0;
     }
     const double dorg = delta[o];
-    for (int it = 0; it < 256; ++it) {
-        const double mid = 0.5 * (lo + hi);
-        if (mid == lo || mid == hi) break;
-        if (secular(delta, zc, kn, rho, dorg, mid) < 0.0) lo = mid;
-        else hi = mid;
+    double tau = 0.5 * (lo + hi);
+    for (int it = 0; it < 100; ++it) {
+        double psi = 0.0, dpsi = 0.0, phi = 0.0, dphi = 0.0;
+        for (int i = 0; i <= j; ++i) {
+            const double r = zc[i] / ((delta[i] - dorg) - tau);
+            psi += zc[i] * r;
+            dpsi += r * r;
+        }
+        for (int i = j + 1; i < kn; ++i) {
+            const double r = zc[i] / ((delta[i] - dorg) - tau);
+            phi += zc[i] * r;
+            dphi += r * r;
+        }
+        psi *= rho;
+        dpsi *= rho;
+        phi *= rho;
+        dphi *= rho;
+        const double f = 1.0 + psi + phi;
+        if (f == 0.0) break;
+        if (f < 0.0) lo = tau;
+        else hi = tau;
+        if (hi - lo <= 4.0 * DEPS * fmax(fabs(lo), fabs(hi))) break;
+        // model: c + s/(D1 - y) + S/(D2 - y) = 0 for the step y from tau
+        const double D1 = (delta[j] - dorg) - tau;
+        double y;
+        bool ok = true;
+        if (!last) {
+            const double D2 = (delta[j + 1] - dorg) - tau;
+            const double sl = dpsi * D1 * D1, sr = dphi * D2 * D2;
+            const double c = f - dpsi * D1 - dphi * D2;
+            const double bq = c * (D1 + D2) + sl + sr;
+            const double cq = c * D1 * D2 + sl * D2 + sr * D1;
+            if (c == 0.0) {
+                y = cq / bq;
+            } else {
+                const double disc = bq * bq - 4.0 * c * cq;
+                if (disc < 0.0) {
+                    ok = false;
+                    y = 0.0;
+                } else {
+                    const double q = 0.5 * (bq + copysign(sqrt(disc), bq));
+                    const double y1 = q / c, y2 = (q != 0.0) ? cq / q : y1;
+                    y = (y1 > D1 && y1 < D2) ? y1 : y2;
+                }
+            }
+        } else {
+            const double sl = dpsi * D1 * D1;
+            const double c = f - dpsi * D1;
+            ok = c > 0.0;
+            y = ok ? D1 + sl / c : 0.0;
+        }
+        double tn = tau + y;
+        if (!ok || !(tn > lo && tn < hi)) tn = 0.5 * (lo + hi);
+        if (fabs(tn - tau) <= 2.0 * DEPS * fabs(tn)) {
+            tau = tn;
+            break;
+        }
+        tau = tn;
     }
-    const double t = 0.5 * (lo + hi);
     org[off + j] = o;
-    tauv[off + j] = t;
-    lam[off + j] = dorg + t;
+    tauv[off + j] = tau;
+    lam[off + j] = dorg + tau;
 }
 
 // z recomputed from the roots (Gu-Eisenstat), products arranged as ratios
