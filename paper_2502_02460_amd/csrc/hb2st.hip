@@ -26,6 +26,7 @@ namespace {
 constexpr int HT = 256;
 constexpr int MAXB = 64;
 constexpr long long SPIN_LIMIT = 200000000LL;
+constexpr int LB = 16;  // independent loads per lane per batch
 
 __device__ inline int ntasks(int n, int b, int sw) { return (n - 1 - sw + b - 1) / b; }
 
@@ -107,22 +108,53 @@ __global__ __launch_bounds__(64) void hb2st_kernel(int n, int b, T* Bw, long ldw
             }
             const int r0 = sw + 1 + t * b;
             const int L = min(b, n - r0);
-            if (t == 0) {
-                if (lane < L) v[lane] = Bw[IDX(1 + lane, sw, ldw)];
+            const int pr0 = r0 - b;  // previous block (t > 0: always b rows)
+            // Stage this task's blocks in LDS with batches of independent
+            // loads (one memory latency per batch, not per element): E =
+            // B[r0.., pr0..] (t > 0) and the lower triangle of D = B[r0.., r0..].
+            {
+                const int ne = (t > 0) ? L * b : 0, nd = L * L;
+                for (int base = 0; base < ne + nd; base += 64 * LB) {
+                    T tmp[LB];
+#pragma unroll
+                    for (int k = 0; k < LB; ++k) {
+                        const int e = base + lane + 64 * k;
+                        tmp[k] = zero_of<T>();
+                        if (e < ne) {
+                            const int i = e % L, j = e / L;
+                            tmp[k] = Bw[IDX(b + i - j, pr0 + j, ldw)];
+                        } else if (e < ne + nd) {
+                            const int f = e - ne, i = f % L, j = f / L;
+                            if (i >= j) tmp[k] = Bw[IDX(i - j, r0 + j, ldw)];
+                        }
+                    }
+#pragma unroll
+                    for (int k = 0; k < LB; ++k) {
+                        const int e = base + lane + 64 * k;
+                        if (e < ne) {
+                            const int i = e % L, j = e / L;
+                            EL_(i, j) = tmp[k];
+                        } else if (e < ne + nd) {
+                            const int f = e - ne, i = f % L, j = f / L;
+                            if (i >= j) {
+                                DL_(i, j) = tmp[k];
+                                DL_(j, i) = conjg(tmp[k]);
+                            }
+                        }
+                    }
+                }
+                if (t == 0 && lane < L) v[lane] = Bw[IDX(1 + lane, sw, ldw)];
                 __syncthreads();
+            }
+            if (t == 0) {
                 reflect1<T>(v, L, sc);
                 if (lane < L) Bw[IDX(1 + lane, sw, ldw)] = (lane == 0) ? sc[1] : zero_of<T>();
             } else {
-                const int pr0 = r0 - b;  // previous block (always b rows)
                 const T pt = ptau;
                 if (lane < L) {
                     const int i = lane;
                     T acc = zero_of<T>();
-                    for (int j = 0; j < b; ++j) {
-                        const T x = Bw[IDX(b + i - j, pr0 + j, ldw)];
-                        EL_(i, j) = x;
-                        acc += x * vp[j];
-                    }
+                    for (int j = 0; j < b; ++j) acc += EL_(i, j) * vp[j];
                     // row i of E (I - ptau vp vp^H)
                     const T pa = pt * acc;
                     for (int j = 0; j < b; ++j) EL_(i, j) -= pa * conjg(vp[j]);
@@ -158,15 +190,6 @@ __global__ __launch_bounds__(64) void hb2st_kernel(int n, int b, T* Bw, long ldw
             // two-sided update of the diagonal block rows/cols r0 .. r0+L-1
             const T tau = sc[0];
             if (!is_zero(tau)) {
-                if (lane < L) {
-                    const int i = lane;
-                    for (int j = 0; j <= i; ++j) {
-                        const T x = Bw[IDX(i - j, r0 + j, ldw)];
-                        DL_(i, j) = x;
-                        DL_(j, i) = conjg(x);
-                    }
-                }
-                __syncthreads();
                 if (lane < L) {
                     T acc = zero_of<T>();
                     for (int j = 0; j < L; ++j) acc += DL_(lane, j) * v[j];

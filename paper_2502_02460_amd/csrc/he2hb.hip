@@ -57,32 +57,56 @@ template <typename T>
 __global__ __launch_bounds__(PT) void panel_step(T* P, long lda, int m, int b, int s, int nref, T* Vp,
                                                  PanelScratch<T>* ps, T* partial) {
     __shared__ T red[PT / WAVE][MAXB + 1];
+    __shared__ T wsh[MAXB];
     __shared__ int last;
     const int tid = threadIdx.x, w = tid / WAVE, l = tid % WAVE;
     const int r0 = s > 0 ? s - 1 : 0;
     const int r = r0 + blockIdx.x * PT + tid;
+    const bool inr = r < m;
+    if (s > 0 && tid < b) wsh[tid] = ps->w[tid];
+    // this thread's row of the panel, columns s-1 .. b-1, in registers
+    // (fully unrolled so the loads are independent and indexing is static)
+    T row[MAXB];
+#pragma unroll
+    for (int j = 0; j < MAXB; ++j) {
+        row[j] = zero_of<T>();
+        if (inr && j + 1 >= s && j < b) row[j] = P[IDX(r, j, lda)];
+    }
+    __syncthreads();
     if (s > 0) {
         const int sp = s - 1;
-        if (r < m) {
-            const T v = (r == sp) ? from_real<T>(1.0) : P[IDX(r, sp, lda)] * ps->scale;
+        T v = zero_of<T>();
+#pragma unroll
+        for (int j = 0; j < MAXB; ++j)
+            if (j == sp) v = (r == sp) ? from_real<T>(1.0) : row[j] * ps->scale;
+        if (inr) {
             Vp[IDX(r, sp, m)] = v;
             const T ctv = conjg(ps->tau[sp]) * v;
-            for (int j = s; j < b; ++j) P[IDX(r, j, lda)] -= ctv * ps->w[j];
+#pragma unroll
+            for (int j = 0; j < MAXB; ++j)
+                if (j >= s && j < b) {
+                    row[j] -= ctv * wsh[j];
+                    P[IDX(r, j, lda)] = row[j];
+                }
         }
         if (blockIdx.x == 0)
             for (int i = tid; i < sp; i += PT) Vp[IDX(i, sp, m)] = zero_of<T>();
     }
     if (s >= nref) return;
-    const bool below = r > s && r < m;
-    const T x = below ? P[IDX(r, s, lda)] : zero_of<T>();
+    const bool below = r > s && inr;
+    T x = zero_of<T>();
+#pragma unroll
+    for (int j = 0; j < MAXB; ++j)
+        if (j == s && below) x = row[j];
     double nx = wave_sum(abs2(x));
     if (l == 0) red[w][MAXB] = from_real<T>(nx);
     const T cx = conjg(x);
-    for (int j = s + 1; j < b; ++j) {
-        T y = below ? cx * P[IDX(r, j, lda)] : zero_of<T>();
-        y = wave_sum(y);
-        if (l == 0) red[w][j] = y;
-    }
+#pragma unroll
+    for (int j = 0; j < MAXB; ++j)
+        if (j > s && j < b) {
+            T y = wave_sum(cx * row[j]);
+            if (l == 0) red[w][j] = y;
+        }
     __syncthreads();
     T* part = partial + (size_t)blockIdx.x * (MAXB + 1);
     if ((tid > s && tid < b) || tid == MAXB) {
@@ -96,7 +120,7 @@ __global__ __launch_bounds__(PT) void panel_step(T* P, long lda, int m, int b, i
     __syncthreads();
     if (!last) return;
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    __shared__ T fin[3];  // tau, scale
+    __shared__ T fin[2];  // tau, scale
     __shared__ double bt;
     if (tid == 0) {
         double xn2 = 0.0;

@@ -354,6 +354,8 @@ __global__ void merge_secular_kernel(const double* e, const MergeDesc* md, const
         dphi *= rho;
         const double f = 1.0 + psi + phi;
         if (f == 0.0) break;
+        // below this the sign of the computed f is not meaningful
+        if (fabs(f) <= 8.0 * DEPS * (1.0 + fabs(psi) + fabs(phi))) break;
         if (f < 0.0) lo = tau;
         else hi = tau;
         if (hi - lo <= 4.0 * DEPS * fmax(fabs(lo), fabs(hi))) break;
