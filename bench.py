@@ -33,7 +33,9 @@ CONFIGS = {
     "c3": (8192, False, 1e-6, 0.30, 3, "real symmetric n=8192, lowest 30%, kappa(S)~1e6"),
 }
 
-FP64_PEAK_TFLOPS = 78.6  # MI355X dense FP64 matrix peak (datasheet)
+FP64_PEAK_TFLOPS = 78.6  # MI355X dense FP64 matrix peak (datasheet); the FP64 vector peak is the same
+# roofline bound of each kernel family
+FAMILY_BOUND = {"gemm": "mfma", "backchase": "mfma", "panel": "alu", "chase": "alu", "dc": "alu", "other": "alu"}
 
 
 def nominal_flops(n: int, k: int, cplx: bool) -> float:
@@ -95,7 +97,7 @@ def main():
     torch.cuda.synchronize()
     print("# inputs drawn in %.1f s (n=%d k=%d %s)" % (time.time() - t0, n, k, "complex" if cplx else "real"),
           file=sys.stderr, flush=True)
-    solver = gevd.Solver(dev, band=args.band, timing=True)
+    solver = gevd.Solver(dev, band=args.band, timing=True, kstats=True)
     H = torch.empty_like(H0)
     S = torch.empty_like(S0)
     C = torch.empty((k, n), dtype=H0.dtype, device=dev).mT
@@ -114,6 +116,7 @@ def main():
     per = []
     phases = []
     torch.cuda.synchronize()
+    solver.reset_kernel_stats()
     tstart = time.perf_counter()
     for i in range(args.steps):
         t1 = time.perf_counter()
@@ -124,6 +127,7 @@ def main():
         print("# step %d: %.3f s" % (i, per[-1]), file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     total = time.perf_counter() - tstart
+    ks = solver.kernel_stats()
     ms = 1e3 * total / args.steps
     fl = nominal_flops(n, k, cplx)
     value = fl / (total / args.steps) / 1e12
@@ -156,6 +160,17 @@ def main():
         "reduction_phases_tflops": round(red_fl / (red_ms / 1e3) / 1e12, 3),
         "reduction_phases_frac_fp64_peak": round(red_fl / (red_ms / 1e3) / 1e12 / FP64_PEAK_TFLOPS, 4),
     }
+    fams = {k: v for k, v in ks.items() if v["launches"] > 0}
+    out["kernels"] = {k: {"launches": v["launches"] // args.steps, "ms_per_step": round(v["ms"] / args.steps, 2),
+                          "tflops": round(v["flops"] / (v["ms"] / 1e3) / 1e12, 3) if v["ms"] > 0 else None}
+                      for k, v in fams.items()}
+    dom = max(fams, key=lambda k: fams[k]["ms"])
+    g = fams[dom]
+    ach = g["flops"] / (g["ms"] / 1e3) / 1e12 if g["ms"] > 0 else 0.0
+    out["roofline"] = {"kernel": dom, "bound": FAMILY_BOUND[dom], "achieved": round(ach, 3),
+                       "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(ach / FP64_PEAK_TFLOPS, 4),
+                       "traffic": None, "launches_per_step": g["launches"] // args.steps,
+                       "avg_launch_ms": round(g["ms"] / g["launches"], 4)}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cplx, n, frac, smin)
     print(json.dumps(out), flush=True)

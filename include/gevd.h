@@ -56,6 +56,16 @@ extern "C" {
 #define GEVD_OPT_BAND 1     /* half-bandwidth b of the intermediate band (0 = auto) */
 #define GEVD_OPT_TIMING 2   /* 1: record per-phase device times (events) */
 #define GEVD_OPT_LEAF 3     /* divide-and-conquer leaf size (0 = auto) */
+#define GEVD_OPT_KSTATS 4   /* 1: time kernel families with HIP events (see gevd_get_kernel_stats) */
+
+/* Kernel families reported by gevd_get_kernel_stats. */
+#define GEVD_K_GEMM 0       /* MFMA matrix products (all shapes, both scalar types) */
+#define GEVD_K_PANEL 1      /* full -> band panel columns */
+#define GEVD_K_CHASE 2      /* band -> tridiagonal bulge chasing */
+#define GEVD_K_BACKCHASE 3  /* back-transformation through the bulge reflectors */
+#define GEVD_K_DC 4         /* divide-and-conquer (leaves, merge steps; merge products count as GEMM) */
+#define GEVD_K_OTHER 5      /* everything else (Cholesky diagonal blocks, T factors, copies) */
+#define GEVD_NKFAM 6
 
 /* Phases reported by gevd_get_timings (milliseconds, last solve). */
 #define GEVD_PH_CHOLESKY 0  /* S = U^H U */
@@ -163,6 +173,15 @@ int gevd_stedc(gevd_handle h, int n, int nev, const double *d, const double *e, 
 /* Per-phase device times (ms) of the last gevd_solve or gevd_eigh when
  * GEVD_OPT_TIMING is on; ms must hold nphase doubles.  Synchronises. */
 int gevd_get_timings(gevd_handle h, double *ms, int nphase);
+
+/* Accumulated accounting of one kernel family (GEVD_K_*) since the option
+ * GEVD_OPT_KSTATS was enabled or the last gevd_reset_kernel_stats: number
+ * of launches, their summed device time in ms (HIP events recorded on the
+ * launch stream around each launch), and the algorithmic flops those
+ * launches perform (real-arithmetic count, a complex multiply-add counting
+ * 8; triangular operands counted by their nonzeros).  Synchronises. */
+int gevd_get_kernel_stats(gevd_handle h, int family, long long *launches, double *ms, double *flops);
+int gevd_reset_kernel_stats(gevd_handle h);
 
 #ifdef __cplusplus
 }

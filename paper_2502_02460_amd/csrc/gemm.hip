@@ -16,6 +16,9 @@
 // store instruction writes 128-byte column segments of the column-major C.
 // Complex products use four real MFMAs per complex k-step (re*re - im*im,
 // re*im + im*re) on separately staged real/imaginary tiles.
+#include <algorithm>
+#include <cstdlib>
+
 #include "kernels.hpp"
 
 namespace gevd {
@@ -23,8 +26,7 @@ namespace {
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
-constexpr int BM = 64, BN = 64, BK = 16, NT = 256;
-constexpr int LDS_PAD = BM + 4;
+constexpr int BK = 16, NT = 256;
 
 template <typename T>
 struct GemmP {
@@ -38,6 +40,7 @@ struct GemmP {
     T alpha, beta;
     int kmode, tmode;
     int tiles_m;
+    int bm, bn;  // workgroup tile (for tile-level triangle tests)
     long long sA, sB, sC;
     int splitk;
     T* work;
@@ -66,16 +69,22 @@ __device__ inline T load_opB(const GemmP<T>& p, const T* B, int l, int j, int ke
 }
 
 
-template <typename T, int OPA, int OPB>
+// Workgroup tile BM x BN = (2 WM) x (2 WN): 4 waves in a 2 x 2 layout, each
+// wave owns WM x WN as (WM/16) x (WN/16) MFMA blocks.
+template <typename T, int OPA, int OPB, int WM, int WN>
 __global__ __launch_bounds__(NT) void gemm_kernel(GemmP<T> p) {
     constexpr bool CX = is_cplx<T>::value;
     constexpr int NC = CX ? 2 : 1;
-    __shared__ double sA[NC][2][BK][LDS_PAD];
-    __shared__ double sB[NC][2][BK][LDS_PAD];
+    constexpr int BM = 2 * WM, BN = 2 * WN;
+    constexpr int FA = WM / 16, FB = WN / 16;  // MFMA blocks per wave
+    constexpr int LA = BM * BK / NT, LB = BN * BK / NT;  // elements loaded per thread
+    __shared__ double sA[NC][2][BK][BM + 4];
+    __shared__ double sB[NC][2][BK][BN + 4];
 
     const int ti = blockIdx.x % p.tiles_m, tj = blockIdx.x / p.tiles_m;
-    if ((p.tmode == T_UPPER_TILES || p.tmode == T_UPPER_STRICT) && ti > tj) return;
-    if ((p.tmode == T_LOWER_TILES || p.tmode == T_LOWER_STRICT) && ti < tj) return;
+    // triangle modes skip tiles whose every element lies on the other side
+    if ((p.tmode == T_UPPER_TILES || p.tmode == T_UPPER_STRICT) && ti * BM > tj * BN + BN - 1) return;
+    if ((p.tmode == T_LOWER_TILES || p.tmode == T_LOWER_STRICT) && ti * BM + BM - 1 < tj * BN) return;
     const T* A = p.A + (long long)blockIdx.y * p.sA;
     const T* B = p.B + (long long)blockIdx.y * p.sB;
     T* C = p.C + (long long)blockIdx.y * p.sC;
@@ -84,8 +93,8 @@ __global__ __launch_bounds__(NT) void gemm_kernel(GemmP<T> p) {
     int kbeg = 0, kend = p.k;
     if (p.kmode == K_B_UPPER) kend = min(kend, j0 + BN);
     if (p.kmode == K_A_LOWER) kend = min(kend, i0 + BM);
-    if (p.kmode == K_A_UPPER) kbeg = i0;
-    if (p.kmode == K_B_LOWER) kbeg = j0;
+    if (p.kmode == K_A_UPPER) kbeg = i0 / BK * BK;
+    if (p.kmode == K_B_LOWER) kbeg = j0 / BK * BK;
     if (p.splitk > 1) {
         int len = max(kend - kbeg, 0);
         int chunk = ((len + p.splitk - 1) / p.splitk + BK - 1) / BK * BK;
@@ -98,25 +107,29 @@ __global__ __launch_bounds__(NT) void gemm_kernel(GemmP<T> p) {
     const int lane = t % WAVE, w = t / WAVE;
     const int wm = w % 2, wn = w / 2;
 
-    dbl4 accR[2][2], accI[2][2];
+    dbl4 accR[FA][FB], accI[FA][FB];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < FA; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
+        for (int b = 0; b < FB; ++b) {
             accR[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
             accI[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
         }
 
-    T ra[4], rb[4];
+    T ra[LA], rb[LB];
     auto gload = [&](int kt) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            int e = t + r * NT;
+        for (int r = 0; r < LA; ++r) {
+            const int e = t + r * NT;
             int ii, ll;
             if (OPA == OP_N) { ii = e % BM; ll = e / BM; }
             else { ii = e / BK; ll = e % BK; }
             ra[r] = load_opA<T, OPA>(p, A, i0 + ii, kt + ll, kend);
-            int jj;
+        }
+#pragma unroll
+        for (int r = 0; r < LB; ++r) {
+            const int e = t + r * NT;
+            int jj, ll;
             if (OPB == OP_N) { ll = e % BK; jj = e / BK; }
             else { jj = e % BN; ll = e / BN; }
             rb[r] = load_opB<T, OPB>(p, B, kt + ll, j0 + jj, kend);
@@ -124,13 +137,18 @@ __global__ __launch_bounds__(NT) void gemm_kernel(GemmP<T> p) {
     };
     auto sstore = [&](int buf) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            int e = t + r * NT;
-            int ii, ll, jj;
+        for (int r = 0; r < LA; ++r) {
+            const int e = t + r * NT;
+            int ii, ll;
             if (OPA == OP_N) { ii = e % BM; ll = e / BM; }
             else { ii = e / BK; ll = e % BK; }
             sA[0][buf][ll][ii] = realp(ra[r]);
             if (CX) sA[NC - 1][buf][ll][ii] = imagp(ra[r]);
+        }
+#pragma unroll
+        for (int r = 0; r < LB; ++r) {
+            const int e = t + r * NT;
+            int jj, ll;
             if (OPB == OP_N) { ll = e % BK; jj = e / BK; }
             else { jj = e % BN; ll = e / BN; }
             sB[0][buf][ll][jj] = realp(rb[r]);
@@ -149,28 +167,41 @@ __global__ __launch_bounds__(NT) void gemm_kernel(GemmP<T> p) {
 #pragma unroll
             for (int kk = 0; kk < BK / 4; ++kk) {
                 const int kr = kk * 4 + lane / 16;
-                double aR[2], bR[2], aI[2], bI[2];
+                double aR[FA], bR[FB], aI[FA], bI[FB];
 #pragma unroll
-                for (int q = 0; q < 2; ++q) {
-                    aR[q] = sA[0][buf][kr][wm * 32 + q * 16 + lane % 16];
-                    bR[q] = sB[0][buf][kr][wn * 32 + q * 16 + lane % 16];
-                    if (CX) {
-                        aI[q] = sA[NC - 1][buf][kr][wm * 32 + q * 16 + lane % 16];
-                        bI[q] = sB[NC - 1][buf][kr][wn * 32 + q * 16 + lane % 16];
-                    }
+                for (int q = 0; q < FA; ++q) {
+                    aR[q] = sA[0][buf][kr][wm * WM + q * 16 + lane % 16];
+                    if (CX) aI[q] = sA[NC - 1][buf][kr][wm * WM + q * 16 + lane % 16];
                 }
 #pragma unroll
-                for (int qa = 0; qa < 2; ++qa)
+                for (int q = 0; q < FB; ++q) {
+                    bR[q] = sB[0][buf][kr][wn * WN + q * 16 + lane % 16];
+                    if (CX) bI[q] = sB[NC - 1][buf][kr][wn * WN + q * 16 + lane % 16];
+                }
+                // D[j][i] += sum_k opB[k][j] opA[i][k]; issued in phases so
+                // that consecutive MFMAs update independent accumulators
 #pragma unroll
-                    for (int qb = 0; qb < 2; ++qb) {
-                        // D[j][i] += sum_k opB[k][j] opA[i][k]
+                for (int qa = 0; qa < FA; ++qa)
+#pragma unroll
+                    for (int qb = 0; qb < FB; ++qb)
                         accR[qa][qb] = __builtin_amdgcn_mfma_f64_16x16x4f64(bR[qb], aR[qa], accR[qa][qb], 0, 0, 0);
-                        if (CX) {
-                            accR[qa][qb] = __builtin_amdgcn_mfma_f64_16x16x4f64(-bI[qb], aI[qa], accR[qa][qb], 0, 0, 0);
+                if (CX) {
+#pragma unroll
+                    for (int qa = 0; qa < FA; ++qa)
+#pragma unroll
+                        for (int qb = 0; qb < FB; ++qb)
                             accI[qa][qb] = __builtin_amdgcn_mfma_f64_16x16x4f64(bI[qb], aR[qa], accI[qa][qb], 0, 0, 0);
+#pragma unroll
+                    for (int qa = 0; qa < FA; ++qa)
+#pragma unroll
+                        for (int qb = 0; qb < FB; ++qb)
+                            accR[qa][qb] = __builtin_amdgcn_mfma_f64_16x16x4f64(-bI[qb], aI[qa], accR[qa][qb], 0, 0, 0);
+#pragma unroll
+                    for (int qa = 0; qa < FA; ++qa)
+#pragma unroll
+                        for (int qb = 0; qb < FB; ++qb)
                             accI[qa][qb] = __builtin_amdgcn_mfma_f64_16x16x4f64(bR[qb], aI[qa], accI[qa][qb], 0, 0, 0);
-                        }
-                    }
+                }
             }
             if (more) sstore(buf ^ 1);
             __syncthreads();
@@ -184,13 +215,13 @@ __global__ __launch_bounds__(NT) void gemm_kernel(GemmP<T> p) {
     const bool strict_up = p.tmode == T_UPPER_STRICT, strict_lo = p.tmode == T_LOWER_STRICT;
     const bool use_beta = !is_zero(p.beta);
 #pragma unroll
-    for (int qa = 0; qa < 2; ++qa)
+    for (int qa = 0; qa < FA; ++qa)
 #pragma unroll
-        for (int qb = 0; qb < 2; ++qb)
+        for (int qb = 0; qb < FB; ++qb)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int row = i0 + wm * 32 + qa * 16 + lane % 16;
-                int col = j0 + wn * 32 + qb * 16 + 4 * r + lane / 16;
+                const int row = i0 + wm * WM + qa * 16 + lane % 16;
+                int col = j0 + wn * WN + qb * 16 + 4 * r + lane / 16;
                 if (row >= p.m || col >= p.n) continue;
                 if (strict_up && row > col) continue;
                 if (strict_lo && row < col) continue;
@@ -214,13 +245,13 @@ __global__ __launch_bounds__(NT) void gemm_kernel(GemmP<T> p) {
 // Deterministic reduction of split-K partials: C = alpha sum_z W_z + beta C.
 template <typename T>
 __global__ void splitk_reduce(int m, int n, int splits, const T* work, T alpha, T beta, T* C, long ldc,
-                              int tmode) {
+                              int tmode, int bm, int bn) {
     long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (long long)m * n) return;
     int row = (int)(idx % m), col = (int)(idx / m);
     if ((tmode == T_UPPER_STRICT && row > col) || (tmode == T_LOWER_STRICT && row < col)) return;
-    if ((tmode == T_UPPER_TILES) && row / BM > col / BN) return;
-    if ((tmode == T_LOWER_TILES) && row / BM < col / BN) return;
+    if ((tmode == T_UPPER_TILES) && (row / bm) * bm > (col / bn) * bn + bn - 1) return;
+    if ((tmode == T_LOWER_TILES) && (row / bm) * bm + bm - 1 < (col / bn) * bn) return;
     T s = zero_of<T>();
     for (int z = 0; z < splits; ++z) s += work[(size_t)z * m * n + idx];
     T out = alpha * s;
@@ -229,15 +260,70 @@ __global__ void splitk_reduce(int m, int n, int splits, const T* work, T alpha, 
 }
 
 template <typename T, int OPA, int OPB>
-void launch_t(hipStream_t st, const GemmP<T>& p, dim3 grid) {
-    hipLaunchKernelGGL((gemm_kernel<T, OPA, OPB>), grid, dim3(NT), 0, st, p);
+void launch_t(hipStream_t st, const GemmP<T>& p, dim3 grid, int cfg) {
+    switch (cfg) {
+        case 1: hipLaunchKernelGGL((gemm_kernel<T, OPA, OPB, 64, 32>), grid, dim3(NT), 0, st, p); break;
+        case 2: hipLaunchKernelGGL((gemm_kernel<T, OPA, OPB, 32, 64>), grid, dim3(NT), 0, st, p); break;
+        case 3: hipLaunchKernelGGL((gemm_kernel<T, OPA, OPB, 64, 64>), grid, dim3(NT), 0, st, p); break;
+        default: hipLaunchKernelGGL((gemm_kernel<T, OPA, OPB, 32, 32>), grid, dim3(NT), 0, st, p); break;
+    }
 }
 
 template <typename T, int OPA>
-void launch_b(hipStream_t st, int opB, const GemmP<T>& p, dim3 grid) {
-    if (opB == OP_N) launch_t<T, OPA, OP_N>(st, p, grid);
-    else if (opB == OP_T) launch_t<T, OPA, OP_T>(st, p, grid);
-    else launch_t<T, OPA, OP_C>(st, p, grid);
+void launch_b(hipStream_t st, int opB, const GemmP<T>& p, dim3 grid, int cfg) {
+    if (opB == OP_N) launch_t<T, OPA, OP_N>(st, p, grid, cfg);
+    else if (opB == OP_T) launch_t<T, OPA, OP_T>(st, p, grid, cfg);
+    else launch_t<T, OPA, OP_C>(st, p, grid, cfg);
+}
+
+// Workgroup tile for a product: 0 = 64x64, 1 = 128x64, 2 = 64x128,
+// 3 = 128x128.  GEVD_GEMM_TILE forces one (for measurements).
+int g_tile_override = -2;  // -2: not read yet, -1: none
+int pick_tile(int m, int n, int k, bool cx) {
+    if (g_tile_override == -2) {
+        const char* e = getenv("GEVD_GEMM_TILE");
+        g_tile_override = e ? atoi(e) : -1;
+    }
+    if (g_tile_override >= 0 && g_tile_override <= 3) return (cx && g_tile_override == 3) ? 1 : g_tile_override;
+    (void)k;
+    (void)cx;
+    if (m >= 1024 && n >= 1024) return cx ? 1 : 3;
+    if (m >= 1024 && n >= 128) return 1;
+    if (n >= 1024 && m >= 128) return 2;
+    return 0;
+}
+
+// Multiply-adds the product needs given its structural zeros and the
+// stored output elements (2 flops each; a complex multiply-add counts 8).
+double algorithmic_flops(int m, int n, int k, int kmode, int tmode, bool cx) {
+    auto kfor = [&](int i, int j) -> double {
+        switch (kmode) {
+            case K_B_UPPER: return std::min(k, j + 1);
+            case K_A_UPPER: return std::max(0, k - i);
+            case K_A_LOWER: return std::min(k, i + 1);
+            case K_B_LOWER: return std::max(0, k - j);
+            default: return k;
+        }
+    };
+    double macs = 0.0;
+    const bool tiles_up = tmode == T_UPPER_TILES || tmode == T_UPPER_STRICT;
+    const bool tiles_lo = tmode == T_LOWER_TILES || tmode == T_LOWER_STRICT;
+    if (kmode == K_FULL && tmode == T_ALL) {
+        macs = (double)m * n * k;
+    } else if (tmode == T_ALL) {
+        if (kmode == K_B_UPPER || kmode == K_B_LOWER)
+            for (int j = 0; j < n; ++j) macs += (double)m * kfor(0, j);
+        else
+            for (int i = 0; i < m; ++i) macs += (double)n * kfor(i, 0);
+    } else {
+        // stored elements: i <= j (upper) or i >= j (lower); the inner
+        // length depends on i only for the modes used with a triangle
+        for (int i = 0; i < m; ++i) {
+            const double cnt = tiles_up ? std::max(0, n - i) : (tiles_lo ? std::min(n, i + 1) : n);
+            macs += cnt * kfor(i, i);
+        }
+    }
+    return 2.0 * macs * (cx ? 4.0 : 1.0);
 }
 
 }  // namespace
@@ -258,20 +344,26 @@ int gemm(hipStream_t st, int opA, int opB, int m, int n, int k, T alpha, const T
     p.A = A; p.lda = lda; p.B = B; p.ldb = ldb; p.C = C; p.ldc = ldc;
     p.alpha = alpha; p.beta = beta;
     p.kmode = kmode; p.tmode = tmode;
-    p.tiles_m = (m + BM - 1) / BM;
-    const int tiles_n = (n + BN - 1) / BN;
+    const int cfg = pick_tile(m, n, k, is_cplx<T>::value);
+    const int bm = (cfg & 1) ? 128 : 64, bn = (cfg & 2) ? 128 : 64;
+    p.bm = bm;
+    p.bn = bn;
+    p.tiles_m = (m + bm - 1) / bm;
+    const int tiles_n = (n + bn - 1) / bn;
     p.sA = batch.sA; p.sB = batch.sB; p.sC = batch.sC;
     p.splitk = splitk; p.work = work;
     p.amap = amap; p.cmap = cmap;
     dim3 grid(p.tiles_m * tiles_n, batch.count, splitk);
-    if (opA == OP_N) launch_b<T, OP_N>(st, opB, p, grid);
-    else if (opA == OP_T) launch_b<T, OP_T>(st, opB, p, grid);
-    else launch_b<T, OP_C>(st, opB, p, grid);
+    KProbe probe(st, GEVD_K_GEMM,
+                 g_kstats ? batch.count * algorithmic_flops(m, n, k, kmode, tmode, is_cplx<T>::value) : 0.0);
+    if (opA == OP_N) launch_b<T, OP_N>(st, opB, p, grid, cfg);
+    else if (opA == OP_T) launch_b<T, OP_T>(st, opB, p, grid, cfg);
+    else launch_b<T, OP_C>(st, opB, p, grid, cfg);
     GEVD_LAUNCH_CHECK();
     if (splitk > 1) {
         long long tot = (long long)m * n;
         hipLaunchKernelGGL(splitk_reduce<T>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, m, n, splitk,
-                           (const T*)work, alpha, beta, C, ldc, tmode);
+                           (const T*)work, alpha, beta, C, ldc, tmode, bm, bn);
         GEVD_LAUNCH_CHECK();
     }
     return 0;

@@ -17,6 +17,10 @@
 
 using namespace gevd;
 
+namespace gevd {
+thread_local KStats* g_kstats = nullptr;
+}
+
 struct gevd_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -29,6 +33,8 @@ struct gevd_ctx {
     hipEvent_t ev[GEVD_NPHASE + 1] = {};
     bool ev_made = false;
     bool ev_valid = false;
+    int kstats_on = 0;
+    KStats ks;
 };
 
 namespace {
@@ -82,6 +88,13 @@ int clear_flags(gevd_ctx* h) {
 void mark(gevd_ctx* h, int phase) {
     if (h->timing && h->ev_made) (void)hipEventRecord(h->ev[phase], h->stream);
 }
+
+// Points the launch probes of this thread at the handle's accounting for the
+// duration of one entry point.
+struct KScope {
+    explicit KScope(gevd_ctx* h) { g_kstats = h->kstats_on ? &h->ks : nullptr; }
+    ~KScope() { g_kstats = nullptr; }
+};
 
 int pick_band(const gevd_ctx* h, int n) {
     int b = h->band_opt > 0 ? h->band_opt : 32;
@@ -198,6 +211,7 @@ int do_solve(gevd_ctx* h, int n, int nev, T* H, int ldh, T* S, int lds, double* 
     if (fl[F_HANG]) return GEVD_E_HANG;
     if (fl[F_NOCONV]) return GEVD_E_NOCONV;
     h->ev_valid = h->timing != 0;
+    if (h->kstats_on) h->ks.settle();  // the stream is idle here
     return 0;
 }
 
@@ -233,6 +247,7 @@ int gevd_destroy(gevd_handle h) {
     if (h->flags) (void)hipFree(h->flags);
     if (h->ev_made)
         for (auto& e : h->ev) (void)hipEventDestroy(e);
+    for (auto& e : h->ks.pool) (void)hipEventDestroy(e);
     delete h;
     return 0;
 }
@@ -262,6 +277,9 @@ int gevd_set_option(gevd_handle h, int option, int value) {
         case GEVD_OPT_LEAF:
             if (value != 0 && (value < 4 || value > 64)) return -3;
             h->leaf_opt = value;
+            return 0;
+        case GEVD_OPT_KSTATS:
+            h->kstats_on = value ? 1 : 0;
             return 0;
         default:
             return -2;
@@ -302,6 +320,7 @@ int gevd_solve(gevd_handle h, int dtype, int n, int nev, void* H, int ldh, void*
     if (!C) return -10;
     if (ldc < n) return -11;
     if (hipSetDevice(h->device) != hipSuccess) return GEVD_E_HIP;
+    KScope kscope(h);
     if (dtype == GEVD_REAL)
         return do_solve<double>(h, n, nev, (double*)H, ldh, (double*)S, lds, eval, (double*)C, ldc);
     return do_solve<zdouble>(h, n, nev, (zdouble*)H, ldh, (zdouble*)S, lds, eval, (zdouble*)C, ldc);
@@ -314,6 +333,7 @@ int gevd_cholesky(gevd_handle h, int dtype, int n, void* S, int lds) {
     if (!S) return -4;
     if (lds < n) return -5;
     if (hipSetDevice(h->device) != hipSuccess) return GEVD_E_HIP;
+    KScope kscope(h);
     int rc = ensure_ws(h, dtype == GEVD_REAL ? plan_cholesky<double>(n) : plan_cholesky<zdouble>(n));
     if (rc) return rc;
     if ((rc = clear_flags(h))) return rc;
@@ -334,6 +354,7 @@ int gevd_invert_upper(gevd_handle h, int dtype, int n, const void* U, int ldu, v
     if (!Uinv) return -6;
     if (ldi < n) return -7;
     if (hipSetDevice(h->device) != hipSuccess) return GEVD_E_HIP;
+    KScope kscope(h);
     int rc = ensure_ws(h, dtype == GEVD_REAL ? plan_invert<double>(n) : plan_invert<zdouble>(n));
     if (rc) return rc;
     return dtype == GEVD_REAL ? do_invert<double>(h, n, (const double*)U, ldu, (double*)Uinv, ldi, h->ws)
@@ -351,6 +372,7 @@ int gevd_reduce(gevd_handle h, int dtype, int n, void* H, int ldh, const void* U
     if (!A) return -8;
     if (lda < n) return -9;
     if (hipSetDevice(h->device) != hipSuccess) return GEVD_E_HIP;
+    KScope kscope(h);
     int rc = ensure_ws(h, dtype == GEVD_REAL ? plan_reduce<double>(n) : plan_reduce<zdouble>(n));
     if (rc) return rc;
     return dtype == GEVD_REAL
@@ -371,6 +393,7 @@ int gevd_backtransform(gevd_handle h, int dtype, int n, int nev, const void* Uin
     if (!C) return -9;
     if (ldc < n) return -10;
     if (hipSetDevice(h->device) != hipSuccess) return GEVD_E_HIP;
+    KScope kscope(h);
     return dtype == GEVD_REAL
                ? do_backtransform<double>(h, n, nev, (const double*)Uinv, ldi, (const double*)Ct, ldct, (double*)C, ldc)
                : do_backtransform<zdouble>(h, n, nev, (const zdouble*)Uinv, ldi, (const zdouble*)Ct, ldct,
@@ -388,6 +411,7 @@ int gevd_eigh(gevd_handle h, int dtype, int n, int nev, void* A, int lda, double
     if (!Z) return -8;
     if (ldz < n) return -9;
     if (hipSetDevice(h->device) != hipSuccess) return GEVD_E_HIP;
+    KScope kscope(h);
     int b = pick_band(h, n);
     size_t need = dtype == GEVD_REAL ? eigh_ws_bytes<double>(n, nev, b, h->leaf_opt)
                                      : eigh_ws_bytes<zdouble>(n, nev, b, h->leaf_opt);
@@ -425,6 +449,7 @@ int gevd_band(gevd_handle h, int dtype, int n, void* A, int lda, void* Bd, int l
     int b = pick_band(h, n);
     if (ldb < b + 1) return -7;
     if (hipSetDevice(h->device) != hipSuccess) return GEVD_E_HIP;
+    KScope kscope(h);
     size_t need = dtype == GEVD_REAL ? band_ws_bytes<double>(n, b) : band_ws_bytes<zdouble>(n, b);
     int rc = ensure_ws(h, need);
     if (rc) return rc;
@@ -442,6 +467,7 @@ int gevd_tridiagonalize(gevd_handle h, int dtype, int n, void* A, int lda, doubl
     if (!d) return -6;
     if (!e && n > 1) return -7;
     if (hipSetDevice(h->device) != hipSuccess) return GEVD_E_HIP;
+    KScope kscope(h);
     int b = pick_band(h, n);
     size_t need = dtype == GEVD_REAL ? eigh_ws_bytes<double>(n, 1, b, h->leaf_opt)
                                      : eigh_ws_bytes<zdouble>(n, 1, b, h->leaf_opt);
@@ -468,6 +494,7 @@ int gevd_stedc(gevd_handle h, int n, int nev, const double* d, const double* e, 
     if (!Z) return -7;
     if (ldz < n) return -8;
     if (hipSetDevice(h->device) != hipSuccess) return GEVD_E_HIP;
+    KScope kscope(h);
     int rc = ensure_ws(h, stedc_ws_bytes(n, nev, h->leaf_opt));
     if (rc) return rc;
     if ((rc = clear_flags(h))) return rc;
@@ -477,6 +504,27 @@ int gevd_stedc(gevd_handle h, int n, int nev, const double* d, const double* e, 
     int fl[NFLAGS];
     if ((rc = read_flags(h, fl))) return rc;
     if (fl[F_NOCONV]) return GEVD_E_NOCONV;
+    return 0;
+}
+
+int gevd_get_kernel_stats(gevd_handle h, int family, long long* launches, double* ms, double* flops) {
+    if (!h) return -1;
+    if (family < 0 || family >= GEVD_NKFAM) return -2;
+    GEVD_HIP(hipSetDevice(h->device));
+    GEVD_HIP(hipStreamSynchronize(h->stream));
+    h->ks.settle();
+    if (launches) *launches = h->ks.tot_n[family];
+    if (ms) *ms = h->ks.tot_ms[family];
+    if (flops) *flops = h->ks.tot_flops[family];
+    return 0;
+}
+
+int gevd_reset_kernel_stats(gevd_handle h) {
+    if (!h) return -1;
+    GEVD_HIP(hipSetDevice(h->device));
+    GEVD_HIP(hipStreamSynchronize(h->stream));
+    h->ks.settle();
+    h->ks.reset();
     return 0;
 }
 

@@ -353,6 +353,34 @@ __global__ __launch_bounds__(256) void back_chase_kernel(int n, int b, int nsw, 
         return (r < lg && q >= 0 && q < b) ? vc[comp][j][q] : 0.0;
     };
 
+    // Next group's reflectors and T factor are fetched into registers while
+    // the current group's products run (software pipelining).
+    constexpr int VPT = NBS * MAXB / 256, TPT = NBS * NBS / 256;
+    T vreg[VPT], treg[TPT];
+    auto fetch = [&](int S, int t) {
+        const int s0 = S * NBS, s1 = min(nsw, s0 + NBS);
+        const T* vsrc = V2 + ((size_t)t * nsw + s0) * b;
+#pragma unroll
+        for (int k = 0; k < VPT; ++k) {
+            const int e = tid + 256 * k;
+            const int j = e / b, s = s0 + j;
+            // reflector slots past the end of the matrix were never written
+            const bool ok = e < NBS * b && s < s1 && s + 1 + t * b < n;
+            vreg[k] = ok ? vsrc[e] : zero_of<T>();
+        }
+        const T* tsrc = Tg + ((size_t)t * nblk + S) * NBS * NBS;
+#pragma unroll
+        for (int k = 0; k < TPT; ++k) treg[k] = tsrc[tid + 256 * k];
+    };
+    auto next_group = [&](int& S, int& t) {  // group order: t ascending within S, S descending
+        if (S * NBS + 1 + (t + 1) * b < n) {
+            ++t;
+        } else {
+            --S;
+            t = 0;
+        }
+    };
+    if (nblk > 0) fetch(nblk - 1, 0);
     for (int S = nblk - 1; S >= 0; --S) {
         const int s0 = S * NBS, s1 = min(nsw, s0 + NBS);
         int lo = -1, hi = -1;
@@ -367,23 +395,27 @@ __global__ __launch_bounds__(256) void back_chase_kernel(int n, int b, int nsw, 
             if (wr1 > la) load_rows(la, wr1);
             lo = wr0;
             hi = wr1;
-            // group reflectors and T
-            // reflector slots past the end of the matrix were never written
-            const T* vsrc = V2 + ((size_t)t * nsw + s0) * b;
-            for (int e = tid; e < NBS * b; e += 256) {
-                const int j = e / b, q = e % b, s = s0 + j;
-                const bool ok = s < s1 && s + 1 + t * b < n;
-                const T v = ok ? vsrc[e] : zero_of<T>();
-                vc[0][j][q] = realp(v);
-                if (CX) vc[NC - 1][j][q] = imagp(v);
+            // this group's reflectors and T (fetched during the previous group)
+#pragma unroll
+            for (int k = 0; k < VPT; ++k) {
+                const int e = tid + 256 * k;
+                if (e < NBS * b) {
+                    vc[0][e / b][e % b] = realp(vreg[k]);
+                    if (CX) vc[NC - 1][e / b][e % b] = imagp(vreg[k]);
+                }
             }
-            const T* tsrc = Tg + ((size_t)t * nblk + S) * NBS * NBS;
-            for (int e = tid; e < NBS * NBS; e += 256) {
-                const T v = tsrc[e];
-                tm[0][e / NBS][e % NBS] = realp(v);
-                if (CX) tm[NC - 1][e / NBS][e % NBS] = imagp(v);
+#pragma unroll
+            for (int k = 0; k < TPT; ++k) {
+                const int e = tid + 256 * k;
+                tm[0][e / NBS][e % NBS] = realp(treg[k]);
+                if (CX) tm[NC - 1][e / NBS][e % NBS] = imagp(treg[k]);
             }
             __syncthreads();
+            {
+                int Sn = S, tn = t;
+                next_group(Sn, tn);
+                if (Sn >= 0) fetch(Sn, tn);
+            }
             const int base = wr0;
             // ---- W = V^H Z: block jb of NBS/16, inner range split in P parts
             {
@@ -481,6 +513,8 @@ int hb2st(const StageCtx& c, int n, T* Bw, long ldw, ChaseRefl<T>& R, double* d,
         const size_t lds = (size_t)2 * b * (b + 1) * sizeof(T);
         GEVD_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&hb2st_kernel<T>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        // algorithmic work: about 6 n^2 b real flops (x4 complex)
+        KProbe probe(st, GEVD_K_CHASE, (is_cplx<T>::value ? 24.0 : 6.0) * (double)n * n * b);
         hipLaunchKernelGGL(hb2st_kernel<T>, dim3(grid), dim3(64), lds, st, n, b, Bw, ldw, R.V2, R.tau2, R.nsw, progress,
                            counter, c.hang);
         GEVD_LAUNCH_CHECK();
@@ -495,10 +529,16 @@ int back_chase(const StageCtx& c, const ChaseRefl<T>& R, int nev, T* Z, long ldz
     if (R.nsw <= 0 || nev <= 0) return 0;
     constexpr int NBS = chase_group<T>();
     if (R.nbs != NBS || R.Tg == nullptr || R.b > MAXB) return GEVD_E_STATE;
-    hipLaunchKernelGGL((chase_tfactor_kernel<T, NBS>), dim3(R.nblk, R.tmax), dim3(256), 0, c.st, R.n, R.b, R.nsw,
-                       R.nblk, (const T*)R.V2, (const T*)R.tau2, R.Tg);
-    GEVD_LAUNCH_CHECK();
+    {
+        KProbe probe(c.st, GEVD_K_OTHER, 0.0);
+        hipLaunchKernelGGL((chase_tfactor_kernel<T, NBS>), dim3(R.nblk, R.tmax), dim3(256), 0, c.st, R.n, R.b,
+                           R.nsw, R.nblk, (const T*)R.V2, (const T*)R.tau2, R.Tg);
+        GEVD_LAUNCH_CHECK();
+    }
     const int grid = (nev + 15) / 16;
+    // algorithmic work: every reflector applied to every column, 4 L nev
+    // real flops each (x4 complex): about 2 n^2 nev in total
+    KProbe probe(c.st, GEVD_K_BACKCHASE, (is_cplx<T>::value ? 8.0 : 2.0) * (double)R.n * R.n * nev);
     hipLaunchKernelGGL((back_chase_kernel<T, NBS>), dim3(grid), dim3(256), 0, c.st, R.n, R.b, R.nsw, R.nblk,
                        (const T*)R.V2, (const T*)R.Tg, nev, Z, ldz);
     GEVD_LAUNCH_CHECK();

@@ -10,6 +10,8 @@
 // all as MFMA products.  The panel QR is latency-bound: each column costs one
 // row-parallel launch whose reductions finish in the last workgroup to
 // arrive (fixed summation order, so results are deterministic).
+#include <algorithm>
+
 #include "stages.hpp"
 
 namespace gevd {
@@ -17,6 +19,7 @@ namespace {
 
 constexpr int PT = 256;    // threads per panel workgroup = rows per workgroup
 constexpr int MAXB = 64;  // largest supported band
+constexpr int GCH = 32;   // partial rows gathered per pass by the last workgroup
 
 template <typename T>
 struct PanelScratch {
@@ -120,14 +123,33 @@ __global__ __launch_bounds__(PT) void panel_step(T* P, long lda, int m, int b, i
     __syncthreads();
     if (!last) return;
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    // gather the workgroups' partials (chunks of GCH rows) into LDS with
+    // independent loads, then add them in workgroup order (deterministic)
     __shared__ T fin[2];  // tau, scale
     __shared__ double bt;
+    __shared__ T gath[GCH][MAXB + 1];
+    __shared__ T acc_lds[MAXB + 1];
+    const int G = gridDim.x;
+    if (tid <= MAXB) acc_lds[tid] = zero_of<T>();
+    for (int g0 = 0; g0 < G; g0 += GCH) {
+        const int rows = min(GCH, G - g0);
+        __syncthreads();
+        for (int e = tid; e < rows * (MAXB + 1); e += PT) {
+            const int g = e / (MAXB + 1), c = e % (MAXB + 1);
+            gath[g][c] = ((c > s && c < b) || c == MAXB) ? partial[(size_t)(g0 + g) * (MAXB + 1) + c] : zero_of<T>();
+        }
+        __syncthreads();
+        if (tid <= MAXB) {
+            T acc = acc_lds[tid];
+            for (int g = 0; g < rows; ++g) acc += gath[g][tid];
+            acc_lds[tid] = acc;
+        }
+    }
+    __syncthreads();
     if (tid == 0) {
-        double xn2 = 0.0;
-        for (unsigned g = 0; g < gridDim.x; ++g) xn2 += realp(partial[(size_t)g * (MAXB + 1) + MAXB]);
         T tau, scale;
         double beta;
-        make_reflector<T>(P[IDX(s, s, lda)], xn2, &tau, &scale, &beta);
+        make_reflector<T>(P[IDX(s, s, lda)], realp(acc_lds[MAXB]), &tau, &scale, &beta);
         fin[0] = tau;
         fin[1] = scale;
         bt = beta;
@@ -137,11 +159,7 @@ __global__ __launch_bounds__(PT) void panel_step(T* P, long lda, int m, int b, i
         ps->counter = 0;
     }
     __syncthreads();
-    if (tid > s && tid < b) {
-        T acc = zero_of<T>();
-        for (unsigned g = 0; g < gridDim.x; ++g) acc += partial[(size_t)g * (MAXB + 1) + tid];
-        ps->w[tid] = conjg(fin[1]) * acc + P[IDX(s, tid, lda)];
-    }
+    if (tid > s && tid < b) ps->w[tid] = conjg(fin[1]) * acc_lds[tid] + P[IDX(s, tid, lda)];
     __syncthreads();
     if (tid == 0) P[IDX(s, s, lda)] = from_real<T>(bt);
 }
@@ -267,6 +285,8 @@ int he2hb(const StageCtx& c, int n, T* A, long lda, BandRefl<T>& R, T* Bd, long 
         for (int s = 0; s <= nref; ++s) {
             const int r0 = s > 0 ? s - 1 : 0;
             const unsigned g = (unsigned)((m - r0 + PT - 1) / PT);
+            KProbe probe(st, GEVD_K_PANEL,
+                         (is_cplx<T>::value ? 16.0 : 4.0) * (double)(m - r0) * std::max(0, b - s));
             hipLaunchKernelGGL(panel_step<T>, dim3(g), dim3(PT), 0, st, P, lda, m, b, s, nref, Vp, w.ps, w.partialT);
             GEVD_LAUNCH_CHECK();
         }
@@ -274,8 +294,11 @@ int he2hb(const StageCtx& c, int n, T* A, long lda, BandRefl<T>& R, T* Bd, long 
         if ((rc = gemm<T>(st, OP_C, OP_N, b, b, m, one, Vp, m, Vp, m, zero, w.G, b, K_FULL, T_ALL, Batch(), SK,
                           w.skS)))
             return rc;
-        hipLaunchKernelGGL(tfactor_kernel<T>, dim3(1), dim3(MAXB), 0, st, b, (const T*)w.G, (const PanelScratch<T>*)w.ps,
-                           Tp);
+        {
+            KProbe probe(st, GEVD_K_OTHER, 0.0);
+            hipLaunchKernelGGL(tfactor_kernel<T>, dim3(1), dim3(MAXB), 0, st, b, (const T*)w.G,
+                               (const PanelScratch<T>*)w.ps, Tp);
+        }
         GEVD_LAUNCH_CHECK();
         // two-sided update of A22 = A[c0+b:, c0+b:]
         T* A22 = A + IDX(c0 + b, c0 + b, lda);

@@ -2,6 +2,7 @@
 #pragma once
 #include "common.hpp"
 #include "../../include/gevd.h"
+#include "kstats.hpp"
 
 namespace gevd {
 

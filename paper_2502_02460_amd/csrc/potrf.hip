@@ -140,9 +140,12 @@ int potrf(hipStream_t st, int n, T* S, long lds, T* work, int* info_dev) {
     const T one = from_real<T>(1.0), mone = from_real<T>(-1.0), zero = zero_of<T>();
     for (int j = 0; j < n; j += NB) {
         const int jb = min(NB, n - j);
-        hipLaunchKernelGGL(potrf_diag_kernel<T>, dim3(1), dim3(NTD), 0, st, jb, S + IDX(j, j, lds), lds, work,
-                           info_dev, j);
-        GEVD_LAUNCH_CHECK();
+        {
+            KProbe probe(st, GEVD_K_OTHER, 0.0);
+            hipLaunchKernelGGL(potrf_diag_kernel<T>, dim3(1), dim3(NTD), 0, st, jb, S + IDX(j, j, lds), lds, work,
+                               info_dev, j);
+            GEVD_LAUNCH_CHECK();
+        }
         const int m2 = n - j - jb;
         if (m2 <= 0) break;
         T* S12 = S + IDX(j, j + jb, lds);

@@ -592,14 +592,20 @@ int stedc_run(const StageCtx& c, int n, int nev, const double* d, const double* 
         if (t.leaf) leaves.push_back({t.off, t.size, t.depth % 2, 0});
     }
     GEVD_HIP(hipMemcpyAsync(w.ld, leaves.data(), sizeof(LeafDesc) * leaves.size(), hipMemcpyHostToDevice, st));
-    hipLaunchKernelGGL(leaf_kernel, dim3((unsigned)leaves.size()), dim3(64), 0, st, n, d, e, eval, w.Z0, w.Z1,
+    {
+            KProbe kp_(st, GEVD_K_DC, 0.0);
+            hipLaunchKernelGGL(leaf_kernel, dim3((unsigned)leaves.size()), dim3(64), 0, st, n, d, e, eval, w.Z0, w.Z1,
                        (const LeafDesc*)w.ld, c.noconv);
     GEVD_LAUNCH_CHECK();
+        }
     if (nodes.size() == 1) {  // a single leaf: parity 0
         const long long tot = (long long)n * nev;
-        hipLaunchKernelGGL(copy_cols_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, n, nev,
+        {
+            KProbe kp_(st, GEVD_K_DC, 0.0);
+            hipLaunchKernelGGL(copy_cols_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, n, nev,
                            (const double*)w.Z0, Z, ldz);
         GEVD_LAUNCH_CHECK();
+        }
         return 0;
     }
     std::vector<MergeDesc> md;
@@ -625,22 +631,34 @@ int stedc_run(const StageCtx& c, int n, int nev, const double* d, const double* 
         {
             const long long tot = 2LL * maxn12;
             const unsigned gx = (unsigned)std::min<long long>((tot + 255) / 256, 4096);
+            {
+            KProbe kp_(st, GEVD_K_DC, 0.0);
             hipLaunchKernelGGL(merge_zero_kernel, dim3(gx, nm), dim3(256), 0, st, n, w.Z0, w.Z1,
                                (const MergeDesc*)w.md);
             GEVD_LAUNCH_CHECK();
         }
+        }
         const unsigned gK = (unsigned)((maxK + 255) / 256);
-        hipLaunchKernelGGL(merge_prep_kernel, dim3(gK, nm), dim3(256), 0, st, n, e, (const double*)eval,
+        {
+            KProbe kp_(st, GEVD_K_DC, 0.0);
+            hipLaunchKernelGGL(merge_prep_kernel, dim3(gK, nm), dim3(256), 0, st, n, e, (const double*)eval,
                            (const double*)w.Z0, (const double*)w.Z1, (const MergeDesc*)w.md, w.dsrt, w.zsrt, w.perm);
         GEVD_LAUNCH_CHECK();
-        hipLaunchKernelGGL(merge_deflate_kernel, dim3((nm + 63) / 64), dim3(64), 0, st, e, (const MergeDesc*)w.md, nm,
+        }
+        {
+            KProbe kp_(st, GEVD_K_DC, 0.0);
+            hipLaunchKernelGGL(merge_deflate_kernel, dim3((nm + 63) / 64), dim3(64), 0, st, e, (const MergeDesc*)w.md, nm,
                            w.dsrt, w.zsrt, w.flag, w.ndl, w.delta, w.zc, w.dfl, w.dval, w.rq1, w.rq2, w.rcs, w.rsn,
                            w.counts);
         GEVD_LAUNCH_CHECK();
-        hipLaunchKernelGGL(merge_rotate_kernel, dim3(gK, nm), dim3(256), 0, st, n, w.Z0, w.Z1,
+        }
+        {
+            KProbe kp_(st, GEVD_K_DC, 0.0);
+            hipLaunchKernelGGL(merge_rotate_kernel, dim3(gK, nm), dim3(256), 0, st, n, w.Z0, w.Z1,
                            (const MergeDesc*)w.md, (const int*)w.perm, (const int*)w.rq1, (const int*)w.rq2,
                            (const double*)w.rcs, (const double*)w.rsn, (const int*)w.counts);
         GEVD_LAUNCH_CHECK();
+        }
         counts.resize(2 * nm);
         GEVD_HIP(hipMemcpyAsync(counts.data(), w.counts, sizeof(int) * 2 * nm, hipMemcpyDeviceToHost, st));
         GEVD_HIP(hipStreamSynchronize(st));
@@ -655,23 +673,35 @@ int stedc_run(const StageCtx& c, int n, int nev, const double* d, const double* 
         GEVD_HIP(hipMemcpyAsync(w.md, md.data(), sizeof(MergeDesc) * nm, hipMemcpyHostToDevice, st));
         if (maxkn > 0) {
             const unsigned gk = (unsigned)((maxkn + 127) / 128);
+            {
+            KProbe kp_(st, GEVD_K_DC, 0.0);
             hipLaunchKernelGGL(merge_secular_kernel, dim3(gk, nm), dim3(128), 0, st, e, (const MergeDesc*)w.md,
                                (const double*)w.delta, (const double*)w.zc, w.org, w.tauv, w.lam);
             GEVD_LAUNCH_CHECK();
+        }
+            {
+            KProbe kp_(st, GEVD_K_DC, 0.0);
             hipLaunchKernelGGL(merge_zhat_kernel, dim3(gk, nm), dim3(128), 0, st, e, (const MergeDesc*)w.md,
                                (const double*)w.delta, (const double*)w.zc, (const int*)w.org,
                                (const double*)w.tauv, w.zhat);
             GEVD_LAUNCH_CHECK();
         }
-        hipLaunchKernelGGL(merge_pos_kernel, dim3(gK, nm), dim3(256), 0, st, (const MergeDesc*)w.md,
+        }
+        {
+            KProbe kp_(st, GEVD_K_DC, 0.0);
+            hipLaunchKernelGGL(merge_pos_kernel, dim3(gK, nm), dim3(256), 0, st, (const MergeDesc*)w.md,
                            (const double*)w.lam, (const double*)w.dval, (const int*)w.dfl, (const int*)w.ndl,
                            (const int*)w.perm, eval, w.posL, w.posD, w.amap, w.cmap, root ? 1 : 0, nev);
         GEVD_LAUNCH_CHECK();
+        }
         if (maxkn > 0) {
+            {
+            KProbe kp_(st, GEVD_K_DC, 0.0);
             hipLaunchKernelGGL(merge_vec_kernel, dim3(maxkn, nm), dim3(256), 0, st, (const MergeDesc*)w.md,
                                (const double*)w.delta, (const int*)w.org, (const double*)w.tauv,
                                (const double*)w.zhat, w.U);
             GEVD_LAUNCH_CHECK();
+        }
         }
         // number of wanted merge-product columns at the root
         std::vector<int> posL;
@@ -706,11 +736,14 @@ int stedc_run(const StageCtx& c, int n, int nev, const double* d, const double* 
             int maxdefl = 0;
             for (auto& M : md) maxdefl = std::max(maxdefl, M.n1 + M.n2 - M.knd);
             if (maxdefl > 0) {
-                hipLaunchKernelGGL(merge_defl_copy_kernel, dim3((maxK + 255) / 256, maxdefl, nm), dim3(256), 0, st, n,
+                {
+            KProbe kp_(st, GEVD_K_DC, 0.0);
+            hipLaunchKernelGGL(merge_defl_copy_kernel, dim3((maxK + 255) / 256, maxdefl, nm), dim3(256), 0, st, n,
                                    (const double*)w.Z0, (const double*)w.Z1, w.Z0, w.Z1, (const MergeDesc*)w.md,
                                    (const int*)w.perm, (const int*)w.dfl, (const int*)w.posD, root ? 1 : 0, nev, Z,
                                    ldz);
                 GEVD_LAUNCH_CHECK();
+        }
             }
         }
     }

@@ -22,7 +22,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 SO_PATH = os.path.join(_HERE, "libgevd.so")
 
 GEVD_REAL, GEVD_COMPLEX = 0, 1
-OPT_BAND, OPT_TIMING, OPT_LEAF = 1, 2, 3
+OPT_BAND, OPT_TIMING, OPT_LEAF, OPT_KSTATS = 1, 2, 3, 4
+KFAMILIES = ("gemm", "panel", "chase", "backchase", "dc", "other")
 PHASES = ("cholesky", "invert", "multiply", "band", "tridiag", "solve", "back2", "back1", "mult")
 E_NONFINITE, E_NOCONV, E_NOMEM, E_HIP, E_STATE, E_HANG = -1001, -1002, -1003, -1004, -1005, -1006
 
@@ -69,6 +70,9 @@ def load():
         L.gevd_tridiagonalize.argtypes = [P, I, I, P, I, P, P]
         L.gevd_stedc.argtypes = [P, I, I, P, P, P, P, I]
         L.gevd_get_timings.argtypes = [P, ctypes.POINTER(D), I]
+        L.gevd_get_kernel_stats.argtypes = [P, I, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(D),
+                                            ctypes.POINTER(D)]
+        L.gevd_reset_kernel_stats.argtypes = [P]
         _lib = L
         return L
 
@@ -115,7 +119,7 @@ class Solver:
     """A library handle bound to one device; keeps its workspace between
     calls.  Work goes to the current torch stream of that device."""
 
-    def __init__(self, device=None, band: int = 0, leaf: int = 0, timing: bool = False):
+    def __init__(self, device=None, band: int = 0, leaf: int = 0, timing: bool = False, kstats: bool = False):
         L = load()
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else
                                    torch.device(device).index or 0)
@@ -128,6 +132,8 @@ class Solver:
             _check(L.gevd_set_option(h, OPT_LEAF, leaf), "gevd_set_option")
         if timing:
             _check(L.gevd_set_option(h, OPT_TIMING, 1), "gevd_set_option")
+        if kstats:
+            _check(L.gevd_set_option(h, OPT_KSTATS, 1), "gevd_set_option")
 
     def close(self):
         if getattr(self, "_h", None):
@@ -233,6 +239,22 @@ class Solver:
         _check(load().gevd_stedc(self._h, n, nev, d.data_ptr(), ee.data_ptr(), w.data_ptr(), Z.data_ptr(), n),
                "gevd_stedc")
         return w, Z
+
+    def kernel_stats(self) -> dict:
+        """Per kernel family: launches, device ms (HIP events on the launch
+        stream) and algorithmic flops, accumulated since the last reset."""
+        out = {}
+        for i, name in enumerate(KFAMILIES):
+            n = ctypes.c_longlong()
+            ms = ctypes.c_double()
+            fl = ctypes.c_double()
+            _check(load().gevd_get_kernel_stats(self._h, i, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(fl)),
+                   "gevd_get_kernel_stats")
+            out[name] = {"launches": n.value, "ms": ms.value, "flops": fl.value}
+        return out
+
+    def reset_kernel_stats(self):
+        _check(load().gevd_reset_kernel_stats(self._h), "gevd_reset_kernel_stats")
 
     def timings(self) -> dict:
         arr = (ctypes.c_double * len(PHASES))()
