@@ -65,7 +65,8 @@ extern "C" {
 #define GEVD_K_BACKCHASE 3  /* back-transformation through the bulge reflectors */
 #define GEVD_K_DC 4         /* divide-and-conquer (leaves, merge steps; merge products count as GEMM) */
 #define GEVD_K_OTHER 5      /* everything else (Cholesky diagonal blocks, T factors, copies) */
-#define GEVD_NKFAM 6
+#define GEVD_K_SMALL 6      /* batched small problems (one fused persistent launch per group) */
+#define GEVD_NKFAM 7
 
 /* Phases reported by gevd_get_timings (milliseconds, last solve). */
 #define GEVD_PH_CHOLESKY 0  /* S = U^H U */
@@ -120,6 +121,20 @@ size_t gevd_workspace_bytes(int dtype, int n, int nev);
  * at minor j; nothing else is computed), or GEVD_E_*. */
 int gevd_solve(gevd_handle h, int dtype, int n, int nev, void *H, int ldh, void *S, int lds,
                double *eval, void *C, int ldc);
+
+/* SCF residency.  In a self-consistent-field loop S is fixed while H changes
+ * every iteration, so the overlap is factored once: gevd_set_overlap reads
+ * the upper triangle of S (not modified), computes U (S = U^H U) and keeps
+ * U^{-1} in device memory owned by the handle (n*n scalars, released by
+ * gevd_destroy or the next gevd_set_overlap).  Synchronises; returns 0, -i,
+ * j > 0 if S is not positive definite at minor j, or GEVD_E_*. */
+int gevd_set_overlap(gevd_handle h, int dtype, int n, const void *S, int lds);
+
+/* Generalized solve with the overlap of the last gevd_set_overlap: the
+ * steps of gevd_solve after the inversion (the two products, the standard
+ * eigenproblem, C = U^{-1} C~).  H (upper triangle read) is clobbered.
+ * Returns GEVD_E_STATE if no overlap is set.  Synchronises. */
+int gevd_solve_resident(gevd_handle h, int nev, void *H, int ldh, double *eval, void *C, int ldc);
 
 /* Step 1: Cholesky factorisation S = U^H U in place (upper triangle read
  * and overwritten with U; the strictly lower triangle is clobbered).
@@ -182,6 +197,67 @@ int gevd_get_timings(gevd_handle h, double *ms, int nphase);
  * 8; triangular operands counted by their nonzeros).  Synchronises. */
 int gevd_get_kernel_stats(gevd_handle h, int family, long long *launches, double *ms, double *flops);
 int gevd_reset_kernel_stats(gevd_handle h);
+
+/* ------------------------------------------------------------------
+ * Batched small problems.  The paper's k-points and spin channels are
+ * independent generalized problems of the same kind (introduction; section
+ * "ELPA - Usability"); when each has order n <= 512 one GPU solves many of
+ * them at once.  A batch is grouped by scalar type and order bucket
+ * (n <= 64, 128, 256, 512); each group is one launch of a persistent fused
+ * kernel whose workgroups take problems from a queue and run the whole
+ * solve of gevd_solve on each one (Cholesky, the reduction by two
+ * triangular solves, one-stage Householder tridiagonalisation, implicit QL,
+ * back-transformation).  Launch shapes (lanes per workgroup, workgroups
+ * per CU) come from the handle's table (gevd_set_batch_shape /
+ * gevd_tune_batched) or a default derived from occupancy.
+ */
+typedef struct {
+    int dtype;     /* GEVD_REAL or GEVD_COMPLEX */
+    int n;         /* order, 1 <= n <= 512 */
+    int nev;       /* wanted eigenpairs (the smallest), 1 <= nev <= n */
+    void *H;       /* device, n x n, upper triangle read; clobbered */
+    int ldh;       /* >= n */
+    void *S;       /* device, n x n, upper triangle read; on return it holds U
+                      (S = U^H U) and the strictly lower triangle U^H */
+    int lds;       /* >= n */
+    double *eval;  /* device, n eigenvalues ascending */
+    void *C;       /* device, n x nev eigenvectors, C^H S C = I */
+    int ldc;       /* >= n */
+} gevd_problem;
+
+typedef struct gevd_batch_s *gevd_batch;
+
+/* Solve `count` problems (array of descriptors in host memory) and write
+ * each problem's status to info[i] (host array of count ints): 0, j > 0 if
+ * S is not positive definite at minor j, GEVD_E_NONFINITE, or
+ * GEVD_E_NOCONV; a failed problem leaves its eval and C undefined and does
+ * not affect the others.  Allocates and frees a small plan (descriptors,
+ * per-workgroup n x n scratch), synchronises.  Returns 0 when the launches
+ * ran, -3 if any descriptor is invalid (nothing is launched), or GEVD_E_*. */
+int gevd_solve_batched(gevd_handle h, int count, const gevd_problem *probs, int *info);
+
+/* A reusable batch for repeated solves on the same buffers (an SCF loop
+ * rewrites H in place each iteration): the descriptors are uploaded and the
+ * launches captured into a HIP graph once; gevd_batch_run replays the graph
+ * on the handle's current stream.  If info is not NULL it receives the
+ * per-problem status (as above) and the call synchronises; otherwise it
+ * returns after enqueueing.  The launch shapes are those of the handle when
+ * the batch was created.  Errors: as gevd_solve_batched. */
+int gevd_batch_create(gevd_handle h, int count, const gevd_problem *probs, gevd_batch *b);
+int gevd_batch_run(gevd_batch b, int *info);
+int gevd_batch_destroy(gevd_batch b);
+
+/* Launch shape of the bucket holding order n: threads per workgroup (64,
+ * 128, 256 or 512; 0 restores the default) and workgroups per CU. */
+int gevd_set_batch_shape(gevd_handle h, int dtype, int n, int threads, int wg_per_cu);
+int gevd_get_batch_shape(gevd_handle h, int dtype, int n, int *threads, int *wg_per_cu);
+
+/* Tune the bucket holding order n: time every candidate shape on `count`
+ * synthetic problems of the bucket's largest order (device-generated,
+ * diagonally dominant S) and keep the fastest in the handle's table; the
+ * chosen shape is returned through threads / wg_per_cu (either may be NULL).
+ * Allocates its own buffers; synchronises. */
+int gevd_tune_batched(gevd_handle h, int dtype, int n, int count, int *threads, int *wg_per_cu);
 
 #ifdef __cplusplus
 }

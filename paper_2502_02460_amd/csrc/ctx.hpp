@@ -1,0 +1,31 @@
+// The handle behind gevd_handle (shared by the host pipeline files).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "kstats.hpp"
+#include "small.hpp"
+
+struct gevd_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int band_opt = 0;
+    int leaf_opt = 0;
+    int timing = 0;
+    char* ws = nullptr;  // workspace (device)
+    size_t ws_bytes = 0;
+    int* flags = nullptr;  // small device status area
+    hipEvent_t ev[GEVD_NPHASE + 1] = {};
+    bool ev_made = false;
+    bool ev_valid = false;
+    int kstats_on = 0;
+    gevd::KStats ks;
+    // resident overlap (SCF reuse): U^{-1} of the last gevd_set_overlap
+    void* uinv = nullptr;
+    size_t uinv_bytes = 0;
+    int res_n = 0, res_dtype = -1;
+    // batched small problems: launch shape per (dtype, order bucket);
+    // 0 = not chosen yet (the default heuristic applies)
+    int bthreads[2][gevd::SMALL_NBUCKET] = {};
+    int bwgpcu[2][gevd::SMALL_NBUCKET] = {};
+    int ncu = 0;
+};

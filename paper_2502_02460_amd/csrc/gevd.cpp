@@ -12,6 +12,7 @@
 #include <cstring>
 #include <new>
 
+#include "ctx.hpp"
 #include "kernels.hpp"
 #include "stages.hpp"
 
@@ -20,22 +21,6 @@ using namespace gevd;
 namespace gevd {
 thread_local KStats* g_kstats = nullptr;
 }
-
-struct gevd_ctx {
-    int device = 0;
-    hipStream_t stream = nullptr;
-    int band_opt = 0;
-    int leaf_opt = 0;
-    int timing = 0;
-    char* ws = nullptr;  // workspace (device)
-    size_t ws_bytes = 0;
-    int* flags = nullptr;  // small device status area
-    hipEvent_t ev[GEVD_NPHASE + 1] = {};
-    bool ev_made = false;
-    bool ev_valid = false;
-    int kstats_on = 0;
-    KStats ks;
-};
 
 namespace {
 
@@ -215,6 +200,71 @@ int do_solve(gevd_ctx* h, int n, int nev, T* H, int ldh, T* S, int lds, double* 
     return 0;
 }
 
+template <typename T>
+int do_set_overlap(gevd_ctx* h, int n, const T* S, int lds) {
+    const size_t need = (size_t)n * n * sizeof(T);
+    if (h->uinv_bytes < need) {
+        if (h->uinv) {
+            GEVD_HIP(hipStreamSynchronize(h->stream));
+            GEVD_HIP(hipFree(h->uinv));
+            h->uinv = nullptr;
+            h->uinv_bytes = 0;
+        }
+        if (hipMalloc(&h->uinv, need) != hipSuccess) {
+            (void)hipGetLastError();
+            return GEVD_E_NOMEM;
+        }
+        h->uinv_bytes = need;
+    }
+    h->res_n = 0;
+    Bump plan(nullptr);
+    plan.take<T>((size_t)n * n);
+    const size_t ws = plan.off + 256 + std::max(plan_cholesky<T>(n), plan_invert<T>(n));
+    int rc = ensure_ws(h, ws);
+    if (rc) return rc;
+    Bump b(h->ws);
+    T* U = b.take<T>((size_t)n * n);
+    char* rest = reinterpret_cast<char*>(b.take<char>(0));
+    if ((rc = clear_flags(h))) return rc;
+    if ((rc = check_finite_upper<T>(h->stream, n, S, lds, h->flags + F_NONFINITE))) return rc;
+    if ((rc = copy_matrix<T>(h->stream, n, n, S, lds, U, n))) return rc;
+    if ((rc = do_cholesky<T>(h, n, U, n, rest))) return rc;
+    int fl[NFLAGS];
+    if ((rc = read_flags(h, fl))) return rc;
+    if (fl[F_NONFINITE]) return GEVD_E_NONFINITE;
+    if (fl[F_INFO]) return fl[F_INFO];
+    if ((rc = do_invert<T>(h, n, U, n, reinterpret_cast<T*>(h->uinv), n, rest))) return rc;
+    if ((rc = read_flags(h, fl))) return rc;
+    h->res_n = n;
+    h->res_dtype = is_cplx<T>::value ? GEVD_COMPLEX : GEVD_REAL;
+    return 0;
+}
+
+template <typename T>
+int do_solve_resident(gevd_ctx* h, int nev, T* H, int ldh, double* eval, T* C, int ldc) {
+    const int n = h->res_n;
+    int rc = ensure_ws(h, plan_solve<T>(h, n, nev));
+    if (rc) return rc;
+    const T* Uinv = reinterpret_cast<const T*>(h->uinv);
+    Bump b(h->ws);
+    b.take<T>((size_t)n * n);  // (the Uinv slot of a full solve, unused here)
+    T* Ct = b.take<T>((size_t)n * nev);
+    char* rest = reinterpret_cast<char*>(b.take<char>(0));
+    if ((rc = clear_flags(h))) return rc;
+    if ((rc = check_finite_upper<T>(h->stream, n, H, ldh, h->flags + F_NONFINITE))) return rc;
+    h->ev_valid = false;
+    if ((rc = do_reduce<T>(h, n, H, ldh, Uinv, n, H, ldh, rest))) return rc;
+    if ((rc = do_eigh<T>(h, n, nev, H, ldh, eval, Ct, n, rest, false))) return rc;
+    if ((rc = do_backtransform<T>(h, n, nev, Uinv, n, Ct, n, C, ldc))) return rc;
+    int fl[NFLAGS];
+    if ((rc = read_flags(h, fl))) return rc;
+    if (fl[F_NONFINITE]) return GEVD_E_NONFINITE;
+    if (fl[F_HANG]) return GEVD_E_HANG;
+    if (fl[F_NOCONV]) return GEVD_E_NOCONV;
+    if (h->kstats_on) h->ks.settle();
+    return 0;
+}
+
 bool bad_dtype(int t) { return t != GEVD_REAL && t != GEVD_COMPLEX; }
 
 }  // namespace
@@ -244,6 +294,7 @@ int gevd_destroy(gevd_handle h) {
     (void)hipSetDevice(h->device);
     (void)hipStreamSynchronize(h->stream);
     if (h->ws) (void)hipFree(h->ws);
+    if (h->uinv) (void)hipFree(h->uinv);
     if (h->flags) (void)hipFree(h->flags);
     if (h->ev_made)
         for (auto& e : h->ev) (void)hipEventDestroy(e);
@@ -324,6 +375,35 @@ int gevd_solve(gevd_handle h, int dtype, int n, int nev, void* H, int ldh, void*
     if (dtype == GEVD_REAL)
         return do_solve<double>(h, n, nev, (double*)H, ldh, (double*)S, lds, eval, (double*)C, ldc);
     return do_solve<zdouble>(h, n, nev, (zdouble*)H, ldh, (zdouble*)S, lds, eval, (zdouble*)C, ldc);
+}
+
+int gevd_set_overlap(gevd_handle h, int dtype, int n, const void* S, int lds) {
+    if (!h) return -1;
+    if (bad_dtype(dtype)) return -2;
+    if (n < 1) return -3;
+    if (!S) return -4;
+    if (lds < n) return -5;
+    if (hipSetDevice(h->device) != hipSuccess) return GEVD_E_HIP;
+    KScope kscope(h);
+    return dtype == GEVD_REAL ? do_set_overlap<double>(h, n, (const double*)S, lds)
+                              : do_set_overlap<zdouble>(h, n, (const zdouble*)S, lds);
+}
+
+int gevd_solve_resident(gevd_handle h, int nev, void* H, int ldh, double* eval, void* C, int ldc) {
+    if (!h) return -1;
+    if (h->res_n < 1) return GEVD_E_STATE;
+    const int n = h->res_n;
+    if (nev < 1 || nev > n) return -2;
+    if (!H) return -3;
+    if (ldh < n) return -4;
+    if (!eval) return -5;
+    if (!C) return -6;
+    if (ldc < n) return -7;
+    if (hipSetDevice(h->device) != hipSuccess) return GEVD_E_HIP;
+    KScope kscope(h);
+    return h->res_dtype == GEVD_REAL
+               ? do_solve_resident<double>(h, nev, (double*)H, ldh, eval, (double*)C, ldc)
+               : do_solve_resident<zdouble>(h, nev, (zdouble*)H, ldh, eval, (zdouble*)C, ldc);
 }
 
 int gevd_cholesky(gevd_handle h, int dtype, int n, void* S, int lds) {

@@ -305,8 +305,9 @@ int he2hb(const StageCtx& c, int n, T* A, long lda, BandRefl<T>& R, T* Bd, long 
         T* Wb = w.LR;                  // columns [0, b): W
         T* Vb = w.LR + (size_t)m * b;  // columns [b, 2b): V
         T* W2 = w.LR + (size_t)2 * m * b;  // columns [2b, 3b): W again
-        if ((rc = gemm<T>(st, OP_N, OP_N, m, b, m, one, A22, lda, Vp, m, zero, w.Y, m, K_FULL, T_ALL, Batch(),
-                          m >= 2048 ? SK : 1, w.skY)))
+        // A22 is kept only in its lower triangle: Y = A22 V reads it as Hermitian
+        if ((rc = gemm<T>(st, OP_N, OP_N, m, b, m, one, A22, lda, Vp, m, zero, w.Y, m, K_A_HERM_LOWER, T_ALL,
+                          Batch(), m >= 2048 ? SK : 1, w.skY)))
             return rc;
         if ((rc = gemm<T>(st, OP_N, OP_N, m, b, b, one, w.Y, m, Tp, b, zero, Wb, m, K_B_UPPER))) return rc;  // X
         if ((rc = gemm<T>(st, OP_C, OP_N, b, b, m, one, Vp, m, Wb, m, zero, w.M1, b, K_FULL, T_ALL, Batch(), SK,
@@ -316,7 +317,9 @@ int he2hb(const StageCtx& c, int n, T* A, long lda, BandRefl<T>& R, T* Bd, long 
         if ((rc = gemm<T>(st, OP_N, OP_N, m, b, b, mhalf, Vp, m, w.M2, b, one, Wb, m))) return rc;  // W
         if ((rc = copy_matrix<T>(st, m, b, Wb, m, W2, m))) return rc;
         if ((rc = copy_matrix<T>(st, m, b, Vp, m, Vb, m))) return rc;
-        if ((rc = gemm<T>(st, OP_N, OP_C, m, m, 2 * b, mone, w.LR, m, Vb, m, one, A22, lda))) return rc;
+        // lower tiles of A22 -= W V^H + V W^H (the upper triangle is never read again)
+        if ((rc = gemm<T>(st, OP_N, OP_C, m, m, 2 * b, mone, w.LR, m, Vb, m, one, A22, lda, K_FULL, T_LOWER_TILES)))
+            return rc;
     }
     const long long tot = (long long)ldb * n;
     hipLaunchKernelGGL(extract_band<T>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, n, b, np, (const T*)A,

@@ -16,6 +16,7 @@ enum KMode {
     K_A_UPPER = 2,  // op(A)[i, l] = 0 for l < i
     K_A_LOWER = 3,  // op(A)[i, l] = 0 for l > i
     K_B_LOWER = 4,  // op(B)[l, j] = 0 for l < j
+    K_A_HERM_LOWER = 5,  // op(A) = A (N) Hermitian, read from its lower triangle only
 };
 // Output tiles computed / elements stored.
 enum TMode {

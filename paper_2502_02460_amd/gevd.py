@@ -13,6 +13,7 @@ Real problems are float64, complex problems complex128.
 from __future__ import annotations
 
 import ctypes
+import json
 import os
 import threading
 
@@ -23,12 +24,20 @@ SO_PATH = os.path.join(_HERE, "libgevd.so")
 
 GEVD_REAL, GEVD_COMPLEX = 0, 1
 OPT_BAND, OPT_TIMING, OPT_LEAF, OPT_KSTATS = 1, 2, 3, 4
-KFAMILIES = ("gemm", "panel", "chase", "backchase", "dc", "other")
+KFAMILIES = ("gemm", "panel", "chase", "backchase", "dc", "other", "small")
+SMALL_MAX = 512
 PHASES = ("cholesky", "invert", "multiply", "band", "tridiag", "solve", "back2", "back1", "mult")
 E_NONFINITE, E_NOCONV, E_NOMEM, E_HIP, E_STATE, E_HANG = -1001, -1002, -1003, -1004, -1005, -1006
 
 _lib = None
 _lock = threading.Lock()
+
+
+class Problem(ctypes.Structure):
+    """gevd_problem of include/gevd.h."""
+    _fields_ = [("dtype", ctypes.c_int), ("n", ctypes.c_int), ("nev", ctypes.c_int),
+                ("H", ctypes.c_void_p), ("ldh", ctypes.c_int), ("S", ctypes.c_void_p), ("lds", ctypes.c_int),
+                ("eval", ctypes.c_void_p), ("C", ctypes.c_void_p), ("ldc", ctypes.c_int)]
 
 
 class GevdError(RuntimeError):
@@ -61,6 +70,8 @@ def load():
         L.gevd_workspace_bytes.restype = ctypes.c_size_t
         L.gevd_solve.argtypes = [P, I, I, I, P, I, P, I, P, P, I]
         L.gevd_cholesky.argtypes = [P, I, I, P, I]
+        L.gevd_set_overlap.argtypes = [P, I, I, P, I]
+        L.gevd_solve_resident.argtypes = [P, I, P, I, P, P, I]
         L.gevd_invert_upper.argtypes = [P, I, I, P, I, P, I]
         L.gevd_reduce.argtypes = [P, I, I, P, I, P, I, P, I]
         L.gevd_eigh.argtypes = [P, I, I, I, P, I, P, P, I]
@@ -73,6 +84,14 @@ def load():
         L.gevd_get_kernel_stats.argtypes = [P, I, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(D),
                                             ctypes.POINTER(D)]
         L.gevd_reset_kernel_stats.argtypes = [P]
+        PP, IP = ctypes.POINTER(Problem), ctypes.POINTER(I)
+        L.gevd_solve_batched.argtypes = [P, I, PP, IP]
+        L.gevd_batch_create.argtypes = [P, I, PP, ctypes.POINTER(P)]
+        L.gevd_batch_run.argtypes = [P, IP]
+        L.gevd_batch_destroy.argtypes = [P]
+        L.gevd_set_batch_shape.argtypes = [P, I, I, I, I]
+        L.gevd_get_batch_shape.argtypes = [P, I, I, IP, IP]
+        L.gevd_tune_batched.argtypes = [P, I, I, I, IP, IP]
         _lib = L
         return L
 
@@ -169,6 +188,25 @@ class Solver:
                                  C.data_ptr(), ldc), "gevd_solve")
         return w, C
 
+    def set_overlap(self, S: torch.Tensor):
+        """Factor S once and keep U^{-1} in the handle (S is not modified)."""
+        n = S.shape[0]
+        self._stream()
+        _check(load().gevd_set_overlap(self._h, _dtype_code(S), n, S.data_ptr(), _ld(S, n, "S")), "gevd_set_overlap")
+        self.res_n, self.res_dtype = n, S.dtype
+
+    def solve_resident(self, H: torch.Tensor, nev: int, C: torch.Tensor | None = None,
+                       eval_out: torch.Tensor | None = None):
+        """Solve with the overlap of the last set_overlap; H is clobbered."""
+        n = H.shape[0]
+        if C is None:
+            C = _empty_cm(n, nev, H.dtype, H.device)
+        w = eval_out if eval_out is not None else torch.empty(n, dtype=torch.float64, device=H.device)
+        self._stream()
+        _check(load().gevd_solve_resident(self._h, nev, H.data_ptr(), _ld(H, n, "H"), w.data_ptr(), C.data_ptr(),
+                                          _ld(C, n, "C")), "gevd_solve_resident")
+        return w, C
+
     def cholesky(self, S: torch.Tensor) -> torch.Tensor:
         n = S.shape[0]
         self._stream()
@@ -240,6 +278,89 @@ class Solver:
                "gevd_stedc")
         return w, Z
 
+    # --------------------------------------------------------- batched small
+    def _problems(self, items, outs):
+        arr = (Problem * len(items))()
+        keep = []
+        for i, (H, S, nev) in enumerate(items):
+            n = H.shape[0]
+            if n > SMALL_MAX:
+                raise ValueError("batched problems need n <= %d (got %d)" % (SMALL_MAX, n))
+            if S.dtype != H.dtype:
+                raise TypeError("H and S must have the same dtype")
+            if outs is None:
+                w = torch.empty(n, dtype=torch.float64, device=H.device)
+                C = _empty_cm(n, nev, H.dtype, H.device)
+            else:
+                w, C = outs[i]
+            keep.append((w, C))
+            arr[i] = Problem(_dtype_code(H), n, nev, H.data_ptr(), _ld(H, n, "H"), S.data_ptr(), _ld(S, n, "S"),
+                             w.data_ptr(), C.data_ptr(), _ld(C, n, "C"))
+        return arr, keep
+
+    def solve_batched(self, items, outs=None):
+        """Solve many small problems in fused persistent launches.
+
+        items: sequence of (H, S, nev) with n <= 512 (H clobbered; S receives
+        U in its upper and U^H in its strictly lower triangle).  outs: optional matching (eval, C)
+        buffers.  Returns (results, info): results[i] = (eval, C) and info[i]
+        the problem's status (0, j > 0 not positive definite at minor j, or an
+        E_* code); raises only for errors of the launch itself."""
+        arr, keep = self._problems(items, outs)
+        info = (ctypes.c_int * len(items))()
+        self._stream()
+        _check(load().gevd_solve_batched(self._h, len(items), arr, info), "gevd_solve_batched")
+        return keep, list(info)
+
+    def batch(self, items, outs=None) -> "Batch":
+        """A reusable batch (descriptors uploaded, launches captured in a HIP
+        graph) over fixed buffers; see Batch.run."""
+        arr, keep = self._problems(items, outs)
+        b = ctypes.c_void_p()
+        self._stream()
+        _check(load().gevd_batch_create(self._h, len(items), arr, ctypes.byref(b)), "gevd_batch_create")
+        return Batch(self, b, keep, list(items))
+
+    def set_batch_shape(self, dtype, n: int, threads: int, wg_per_cu: int):
+        _check(load().gevd_set_batch_shape(self._h, _dt(dtype), n, threads, wg_per_cu), "gevd_set_batch_shape")
+
+    def batch_shape(self, dtype, n: int):
+        t, w = ctypes.c_int(), ctypes.c_int()
+        _check(load().gevd_get_batch_shape(self._h, _dt(dtype), n, ctypes.byref(t), ctypes.byref(w)),
+               "gevd_get_batch_shape")
+        return t.value, w.value
+
+    def tune_batched(self, dtype, n: int, count: int = 512):
+        """Run the launch-shape tuner for the bucket holding order n."""
+        t, w = ctypes.c_int(), ctypes.c_int()
+        self._stream()
+        _check(load().gevd_tune_batched(self._h, _dt(dtype), n, count, ctypes.byref(t), ctypes.byref(w)),
+               "gevd_tune_batched")
+        return t.value, w.value
+
+    def load_batch_shapes(self, path: str) -> int:
+        """Apply tuned shapes saved by save_batch_shapes; returns how many."""
+        if not os.path.exists(path):
+            return 0
+        with open(path) as f:
+            table = json.load(f)
+        k = 0
+        for key, (t, w) in table.items():
+            dt, n = key.split(":")
+            self.set_batch_shape(torch.complex128 if dt == "z" else torch.float64, int(n), int(t), int(w))
+            k += 1
+        return k
+
+    def save_batch_shapes(self, path: str, buckets=(64, 128, 256, 512)):
+        table = {}
+        for dt, tag in ((torch.float64, "d"), (torch.complex128, "z")):
+            for n in buckets:
+                table["%s:%d" % (tag, n)] = list(self.batch_shape(dt, n))
+        tmp = path + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(table, f, indent=1, sort_keys=True)
+        os.replace(tmp, path)
+
     def kernel_stats(self) -> dict:
         """Per kernel family: launches, device ms (HIP events on the launch
         stream) and algorithmic flops, accumulated since the last reset."""
@@ -260,6 +381,45 @@ class Solver:
         arr = (ctypes.c_double * len(PHASES))()
         _check(load().gevd_get_timings(self._h, arr, len(PHASES)), "gevd_get_timings")
         return dict(zip(PHASES, list(arr)))
+
+
+class Batch:
+    """A captured batch: run() replays it on the solver's current stream."""
+
+    def __init__(self, solver: Solver, handle, results, items):
+        self.solver = solver
+        self._b = handle
+        self.results = results  # [(eval, C)] in item order
+        self.items = items      # keeps the input tensors alive
+
+    def run(self, sync: bool = True):
+        """Replay; with sync, wait and return the per-problem info list."""
+        self.solver._stream()
+        if sync:
+            info = (ctypes.c_int * len(self.results))()
+            _check(load().gevd_batch_run(self._b, info), "gevd_batch_run")
+            return list(info)
+        _check(load().gevd_batch_run(self._b, None), "gevd_batch_run")
+        return None
+
+    def close(self):
+        if getattr(self, "_b", None):
+            load().gevd_batch_destroy(self._b)
+            self._b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _dt(dtype) -> int:
+    if dtype in (torch.complex128, GEVD_COMPLEX, "z", "complex"):
+        return GEVD_COMPLEX
+    if dtype in (torch.float64, GEVD_REAL, "d", "real"):
+        return GEVD_REAL
+    raise TypeError("dtype must be float64 or complex128, got %r" % (dtype,))
 
 
 def workspace_bytes(dtype, n: int, nev: int) -> int:

@@ -1,0 +1,110 @@
+"""Batched small problems (n <= 512) in the fused persistent kernel.
+
+Parity against the oracle problem by problem (eigenvalues normwise,
+backward error, S-orthonormality, the same gates as the single solve);
+every result of a mixed batch equals the same problem solved alone, bit for
+bit (each problem is one workgroup's work, independent of its neighbours);
+graph replays equal the eager launch; a failing problem reports its own
+status and leaves the rest intact; the shape tuner returns a valid shape."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2502_02460_amd import synth
+from tests.gpu_util import dev, host, log
+from tests.linalg_checks import backward_errors, s_orthonormality
+
+pytestmark = pytest.mark.gpu
+
+# (n, complex, sigma_min, fraction wanted): bucket edges, ragged orders,
+# the degenerate n = 1 and 2, and the largest order
+MIX = [(1, False, 1e-3, 1.0), (2, True, 1e-3, 1.0), (7, False, 1e-3, 1.0), (64, True, 1e-6, 0.3),
+       (65, False, 1e-6, 0.3), (128, False, 1e-3, 1.0), (130, True, 1e-6, 0.3), (256, True, 1e-6, 0.3),
+       (257, False, 1e-6, 0.3), (512, False, 1e-6, 0.3), (512, True, 1e-6, 0.3), (333, True, 1e-3, 0.5)]
+
+
+def _pencils():
+    return [synth.pencil(n, c, smin, 4000 + i, frac) for i, (n, c, smin, frac) in enumerate(MIX)]
+
+
+def _items(ps):
+    return [(dev(p.H), dev(p.S), p.k) for p in ps]
+
+
+@pytest.fixture(scope="module")
+def solver(gpu_lib):
+    s = gpu_lib.Solver()
+    yield s
+    s.close()
+
+
+def test_batched_matches_oracle(solver):
+    ps = _pencils()
+    res, info = solver.solve_batched(_items(ps))
+    assert info == [0] * len(ps)
+    for p, (w, C) in zip(ps, res):
+        w, C = host(w), host(C)
+        w_ref, C_ref, _ = oracle.gevd(p.H, p.S, p.k)
+        err = np.abs(w - w_ref).max() / np.abs(w_ref).max()
+        eta = backward_errors(p.H, p.S, w[: p.k], C).max()
+        orth, orth_ref = s_orthonormality(p.S, C), s_orthonormality(p.S, C_ref)
+        log(f"batched n={p.H.shape[0]} k={p.k} cplx={np.iscomplexobj(p.H)}: eig {err:.2e} eta {eta:.2e} "
+            f"orth {orth:.2e} (oracle {orth_ref:.2e})")
+        assert err < 1e-10 and eta < 1e-11
+        assert orth < max(1e-11, 10 * orth_ref)
+
+
+def test_batched_equals_alone_and_graph_replay(solver):
+    ps = _pencils()
+    res, info = solver.solve_batched(_items(ps))
+    assert info == [0] * len(ps)
+    mix = [(host(w), host(C)) for w, C in res]
+    for i in (0, 3, 9, 10):  # alone, one at a time
+        (w, C), = solver.solve_batched([_items([ps[i]])[0]])[0]
+        assert np.array_equal(host(w), mix[i][0]) and np.array_equal(host(C), mix[i][1])
+    # captured batch over fixed buffers, inputs rewritten before each replay
+    items = _items(ps)
+    pristine = [(H.clone(), S.clone()) for H, S, _ in items]
+    b = solver.batch(items)
+    for rep in range(3):
+        for (H, S, _), (H0, S0) in zip(items, pristine):
+            H.copy_(H0)
+            S.copy_(S0)
+        torch.cuda.synchronize()
+        assert b.run() == [0] * len(ps)
+        for (w, C), (w0, C0) in zip(b.results, mix):
+            assert np.array_equal(host(w), w0) and np.array_equal(host(C), C0)
+        log(f"graph replay {rep}: identical to the eager batch")
+    b.close()
+
+
+def test_failures_stay_local(solver):
+    ps = [synth.pencil(n, c, 1e-3, 77 + n, 0.5) for n, c in ((40, False), (90, True), (200, False))]
+    items = _items(ps)
+    bad_S = ps[1].S.copy()
+    bad_S[5, 5] = -1.0  # leading minor 6 is not positive definite
+    items[1] = (dev(ps[1].H), dev(bad_S), ps[1].k)
+    bad_H = ps[2].H.copy()
+    bad_H[3, 10] = np.nan
+    items[2] = (dev(bad_H), dev(ps[2].S), ps[2].k)
+    items.append(_items([ps[0]])[0])
+    res, info = solver.solve_batched(items)
+    assert info[0] == 0 and info[3] == 0
+    assert info[1] > 0 and info[1] <= 6
+    assert info[2] == -1001
+    assert np.array_equal(host(res[0][0]), host(res[3][0]))
+
+
+def test_tuner_and_shapes(gpu_lib, solver):
+    t, w = solver.tune_batched(torch.float64, 60, count=96)
+    assert t in (64, 128, 256, 512) and w >= 1
+    assert solver.batch_shape(torch.float64, 33) == (t, w)
+    p = synth.pencil(60, False, 1e-3, 5, 1.0)
+    (wv, C), = solver.solve_batched(_items([p]))[0]
+    w_ref, _, _ = oracle.gevd(p.H, p.S, p.k)
+    assert np.abs(host(wv) - w_ref).max() / np.abs(w_ref).max() < 1e-10
+    solver.set_batch_shape(torch.float64, 60, 0, 0)  # back to the default
+    log(f"tuned shape for real n<=64: {t} lanes, {w} workgroups per CU")
