@@ -223,7 +223,13 @@ typedef struct {
     double *eval;  /* device, n eigenvalues ascending */
     void *C;       /* device, n x nev eigenvectors, C^H S C = I */
     int ldc;       /* >= n */
+    int flags;     /* 0 or GEVD_PROBLEM_FACTORED */
 } gevd_problem;
+
+/* S already holds U (upper) and U^H (strictly lower) from an earlier solve
+ * of this same S by the batched entry points: the Cholesky step is skipped
+ * (SCF iterations with a fixed overlap reuse the factor). */
+#define GEVD_PROBLEM_FACTORED 1
 
 typedef struct gevd_batch_s *gevd_batch;
 

@@ -16,9 +16,13 @@ using namespace gevd;
 
 namespace {
 
+// One group per scalar type: a single queue over all its problems, largest
+// order first (longest-processing-time order balances the persistent
+// workgroups); LDS and Z slots are sized for the group's largest order.
 struct Group {
     bool cx;
     int bucket, first, count, threads, grid;
+    long zoff;
 };
 
 double problem_flops(const gevd_problem& p) {
@@ -26,7 +30,8 @@ double problem_flops(const gevd_problem& p) {
     // tridiagonalisation 4n^3/3, back-transformation 2n^2 k + n^2 k (real
     // count; x4 complex).  QL rotations are not counted.
     const double n = p.n, k = p.nev;
-    const double f = n * n * n / 3.0 + 2.0 * n * n * n + 4.0 * n * n * n / 3.0 + 3.0 * n * n * k;
+    const double chol = (p.flags & GEVD_PROBLEM_FACTORED) ? 0.0 : n * n * n / 3.0;
+    const double f = chol + 2.0 * n * n * n + 4.0 * n * n * n / 3.0 + 3.0 * n * n * k;
     return p.dtype == GEVD_COMPLEX ? 4.0 * f : f;
 }
 
@@ -60,6 +65,7 @@ int check_problem(const gevd_problem& p) {
     if (p.n < 1 || p.n > SMALL_MAX || p.nev < 1 || p.nev > p.n) return 1;
     if (!p.H || !p.S || !p.C || !p.eval) return 1;
     if (p.ldh < p.n || p.lds < p.n || p.ldc < p.n) return 1;
+    if (p.flags & ~GEVD_PROBLEM_FACTORED) return 1;
     return 0;
 }
 
@@ -77,6 +83,8 @@ struct gevd_batch_s {
     bool graphed = false;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+    hipStream_t aux = nullptr;  // second stream: the two scalar types run concurrently
 };
 
 namespace {
@@ -89,16 +97,31 @@ void release(gevd_batch_s* b) {
     if (b->info) (void)hipFree(b->info);
     if (b->counters) (void)hipFree(b->counters);
     if (b->zws) (void)hipFree(b->zws);
+    if (b->fork) (void)hipEventDestroy(b->fork);
+    if (b->join) (void)hipEventDestroy(b->join);
+    if (b->aux) (void)hipStreamDestroy(b->aux);
     delete b;
 }
 
-int enqueue(gevd_batch_s* b, hipStream_t st) {
-    for (size_t g = 0; g < b->groups.size(); ++g) {
-        const Group& G = b->groups[g];
-        const int rc = small_launch(st, G.cx, G.threads, G.grid, small_bucket_n(G.bucket), b->desc + G.first, G.count,
-                                    b->zws, b->counters + g);
-        if (rc) return rc;
+int launch_group(gevd_batch_s* b, size_t g, hipStream_t st) {
+    const Group& G = b->groups[g];
+    return small_launch(st, G.cx, G.threads, G.grid, small_bucket_n(G.bucket), b->desc + G.first, G.count,
+                        b->zws + G.zoff, b->counters + g);
+}
+
+// The first group on st; a second one on st2, forked from and joined back
+// into st with events (also inside a graph capture, where this makes two
+// parallel branches).
+int enqueue(gevd_batch_s* b, hipStream_t st, hipStream_t st2) {
+    int rc = 0;
+    if (b->groups.size() > 1) {
+        GEVD_HIP(hipEventRecord(b->fork, st));
+        GEVD_HIP(hipStreamWaitEvent(st2, b->fork, 0));
+        if ((rc = launch_group(b, 1, st2))) return rc;
+        GEVD_HIP(hipEventRecord(b->join, st2));
     }
+    if ((rc = launch_group(b, 0, st))) return rc;
+    if (b->groups.size() > 1) GEVD_HIP(hipStreamWaitEvent(st, b->join, 0));
     return 0;
 }
 
@@ -113,7 +136,8 @@ int build(gevd_ctx* h, int count, const gevd_problem* probs, bool graphed, gevd_
     // order: by (dtype, bucket), largest order first inside a bucket
     std::vector<int> ord(count);
     for (int i = 0; i < count; ++i) ord[i] = i;
-    auto key = [&](int i) { return (probs[i].dtype == GEVD_COMPLEX ? 1 : 0) * SMALL_NBUCKET + small_bucket(probs[i].n); };
+    // complex first: its group is the longer one and goes on the main stream
+    auto key = [&](int i) { return probs[i].dtype == GEVD_COMPLEX ? 0 : 1; };
     std::stable_sort(ord.begin(), ord.end(), [&](int a, int c) {
         if (key(a) != key(c)) return key(a) < key(c);
         return probs[a].n > probs[c].n;
@@ -121,7 +145,7 @@ int build(gevd_ctx* h, int count, const gevd_problem* probs, bool graphed, gevd_
     int rc = 0;
     if (hipMalloc(&b->desc, sizeof(SmallDesc) * count) != hipSuccess ||
         hipMalloc(&b->info, sizeof(int) * count) != hipSuccess ||
-        hipMalloc(&b->counters, sizeof(int) * 2 * SMALL_NBUCKET) != hipSuccess) {
+        hipMalloc(&b->counters, sizeof(int) * 2) != hipSuccess) {
         (void)hipGetLastError();
         release(b);
         return GEVD_E_NOMEM;
@@ -133,8 +157,8 @@ int build(gevd_ctx* h, int count, const gevd_problem* probs, bool graphed, gevd_
         int e = s;
         while (e < count && key(ord[e]) == k) ++e;
         Group G;
-        G.cx = k >= SMALL_NBUCKET;
-        G.bucket = k % SMALL_NBUCKET;
+        G.cx = k == 0;
+        G.bucket = small_bucket(probs[ord[s]].n);  // largest order of the group
         G.first = s;
         G.count = e - s;
         int wg = 1;
@@ -144,13 +168,15 @@ int build(gevd_ctx* h, int count, const gevd_problem* probs, bool graphed, gevd_
             release(b);
             return rc;
         }
-        zmax = std::max(zmax, (long)G.grid * small_zslot(small_bucket_n(G.bucket)));
+        G.zoff = zmax;
+        zmax += (long)G.grid * small_zslot(small_bucket_n(G.bucket));
         b->groups.push_back(G);
         s = e;
     }
     for (int s = 0; s < count; ++s) {
         const gevd_problem& p = probs[ord[s]];
-        hd[s] = SmallDesc{p.H, p.S, p.C, p.eval, b->info + ord[s], (long)p.ldh, (long)p.lds, (long)p.ldc, p.n, p.nev};
+        hd[s] = SmallDesc{p.H, p.S, p.C, p.eval, b->info + ord[s], (long)p.ldh, (long)p.lds, (long)p.ldc, p.n, p.nev,
+                          (p.flags & GEVD_PROBLEM_FACTORED) ? 1 : 0};
         b->flops += problem_flops(p);
     }
     if (hipMalloc(&b->zws, sizeof(double) * std::max(zmax, 1L)) != hipSuccess) {
@@ -158,22 +184,30 @@ int build(gevd_ctx* h, int count, const gevd_problem* probs, bool graphed, gevd_
         release(b);
         return GEVD_E_NOMEM;
     }
-    if (hipMemcpy(b->desc, hd.data(), sizeof(SmallDesc) * count, hipMemcpyHostToDevice) != hipSuccess) {
+    if (hipMemcpy(b->desc, hd.data(), sizeof(SmallDesc) * count, hipMemcpyHostToDevice) != hipSuccess ||
+        hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&b->join, hipEventDisableTiming) != hipSuccess ||
+        (!graphed && b->groups.size() > 1 && hipStreamCreateWithFlags(&b->aux, hipStreamNonBlocking) != hipSuccess)) {
+        (void)hipGetLastError();
         release(b);
         return GEVD_E_HIP;
     }
     if (graphed) {
-        hipStream_t cs = nullptr;
-        if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
+        hipStream_t cs = nullptr, cs2 = nullptr;
+        if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess ||
+            hipStreamCreateWithFlags(&cs2, hipStreamNonBlocking) != hipSuccess) {
+            (void)hipGetLastError();
+            if (cs) (void)hipStreamDestroy(cs);
             release(b);
             return GEVD_E_HIP;
         }
         bool ok = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed) == hipSuccess;
         if (ok) {
-            rc = enqueue(b, cs);
+            rc = enqueue(b, cs, cs2);
             ok = hipStreamEndCapture(cs, &b->graph) == hipSuccess && rc == 0;
         }
         if (ok) ok = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) == hipSuccess;
+        (void)hipStreamDestroy(cs2);
         (void)hipStreamDestroy(cs);
         if (!ok) {
             (void)hipGetLastError();
@@ -195,7 +229,7 @@ int run(gevd_batch_s* b, int* info) {
         if (b->graphed) {
             if (hipGraphLaunch(b->exec, h->stream) != hipSuccess) rc = GEVD_E_HIP;
         } else {
-            rc = enqueue(b, h->stream);
+            rc = enqueue(b, h->stream, b->aux);
         }
         if (rc) {
             g_kstats = nullptr;
@@ -307,7 +341,7 @@ int gevd_tune_batched(gevd_handle h, int dtype, int n, int count, int* threads, 
     const int nev = std::max(1, (3 * nb) / 10);
     for (int p = 0; p < count; ++p)
         probs[p] = gevd_problem{dtype, nb, nev, H + es * per * p, nb, S + es * per * p, nb, ev + (long)nb * p,
-                                C + es * per * p, nb};
+                                C + es * per * p, nb, 0};
     hipEvent_t e0, e1;
     GEVD_HIP(hipEventCreate(&e0));
     GEVD_HIP(hipEventCreate(&e1));
@@ -329,7 +363,7 @@ int gevd_tune_batched(gevd_handle h, int dtype, int n, int count, int* threads, 
             for (int rep = 0; rep < 2 && !rc; ++rep) {
                 if ((rc = small_gen(h->stream, cx, nb, count, H, S, per, 1234 + rep))) break;
                 if (hipEventRecord(e0, h->stream) != hipSuccess) rc = GEVD_E_HIP;
-                if (!rc) rc = enqueue(b, h->stream);
+                if (!rc) rc = enqueue(b, h->stream, b->aux);
                 if (!rc && hipEventRecord(e1, h->stream) != hipSuccess) rc = GEVD_E_HIP;
                 if (!rc && hipEventSynchronize(e1) != hipSuccess) rc = GEVD_E_HIP;
                 float ms = 0.f;

@@ -57,6 +57,28 @@ __host__ __device__ inline size_t lds_layout(int nmax, Lds<T>* L, char* base) {
 __device__ inline double shfl_s(double v, int src) { return __shfl(v, src, WAVE); }
 __device__ inline zdouble shfl_s(zdouble v, int src) { return {__shfl(v.x, src, WAVE), __shfl(v.y, src, WAVE)}; }
 
+// Sum of x(i), 0 <= i < len, in an order that does not depend on the
+// workgroup size: 64-element chunks reduced by the wave butterfly (the same
+// tree in every lane), chunk sums added in chunk order.  A problem's result
+// is then the same whatever launch shape runs it.  chunk holds
+// SMALL_MAX / 64 entries.
+template <int NT, typename U, typename F>
+__device__ U chunked_sum(int len, F x, U* chunk) {
+    const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
+    const int nch = (len + WAVE - 1) / WAVE;
+    __syncthreads();
+    for (int c = wv; c < nch; c += NT / WAVE) {
+        const int i = c * WAVE + lane;
+        U v = i < len ? x(i) : zero_of<U>();
+        v = wave_sum(v);
+        if (lane == 0) chunk[c] = v;
+    }
+    __syncthreads();
+    U t = zero_of<U>();
+    for (int c = 0; c < nch; ++c) t += chunk[c];
+    return t;
+}
+
 // ---------------------------------------------------------------------------
 // 1. Cholesky.  Reads the upper triangle of S; writes L = U^H into the lower
 // triangle and U into the upper one (diagonal shared).  Column blocks of RB:
@@ -200,9 +222,8 @@ __device__ void tridiag_small(T* A, long lda, int n, Lds<T>& L, T* red, double* 
             for (int i = j + tid; i < n; i += NT) A[IDX(i, j, lda)] -= v[i - j] * conjg(wj) + w[i - j] * conjg(vj);
             __syncthreads();
         }
-        double part = 0.0;
-        for (int i = 1 + tid; i < len; i += NT) part += abs2(A[IDX(o + i, j, lda)]);
-        part = block_sum<NT>(part, redd);
+        const double part =
+            chunked_sum<NT, double>(len, [&](int i) { return i > 0 ? abs2(A[IDX(o + i, j, lda)]) : 0.0; }, redd);
         if (tid == 0) {
             const T alpha = A[IDX(o, j, lda)];
             const double ar = realp(alpha), ai = imagp(alpha);
@@ -221,10 +242,10 @@ __device__ void tridiag_small(T* A, long lda, int n, Lds<T>& L, T* red, double* 
             L.tau[j] = tau;
             L.e[j] = beta;
             L.d[j] = realp(A[IDX(j, j, lda)]);
-            red[NT / WAVE] = scale;
+            red[QMAX] = scale;
         }
         __syncthreads();
-        const T tau = L.tau[j], scale = red[NT / WAVE];
+        const T tau = L.tau[j], scale = red[QMAX];
         for (int i = tid; i < len; i += NT) {
             if (i == 0) {
                 v2[0] = from_real<T>(1.0);
@@ -250,10 +271,7 @@ __device__ void tridiag_small(T* A, long lda, int n, Lds<T>& L, T* red, double* 
             }
             y2[i - o] = tau * acc;
         }
-        // each lane reads back only the y2 entries it wrote
-        T part2 = zero_of<T>();
-        for (int i = tid; i < len; i += NT) part2 += conjg(y2[i]) * v2[i];
-        const T yv = block_sum<NT>(part2, red);
+        const T yv = chunked_sum<NT, T>(len, [&](int i) { return conjg(y2[i]) * v2[i]; }, red);
         const T coef = from_real<T>(-0.5) * tau * yv;
         for (int i = tid; i < len; i += NT) y2[i] = y2[i] + coef * v2[i];
         __syncthreads();
@@ -276,10 +294,19 @@ __device__ void tridiag_small(T* A, long lda, int n, Lds<T>& L, T* red, double* 
 
 // ---------------------------------------------------------------------------
 // 4. Implicit QL with the shift from the leading 2x2 of the unreduced block
-// (the classical tql2 iteration).  Lane 0 forms the rotations of a sweep;
-// all lanes apply them to the rows of Z.  Returns false if an eigenvalue took
-// more than 30 sweeps.
+// (the classical tql2 iteration).  The first wave finds the end m of the
+// unreduced block with one ballot per 64 entries; its lane 0 then forms the
+// rotations of the sweep, a serial recurrence kept short: every d and e a
+// step reads is a value the sweep has not yet overwritten, so it is loaded
+// one step ahead, and each rotation takes one reciprocal.  All lanes apply
+// the sweep to the rows of Z.  Returns false if an eigenvalue took more than
+// 30 sweeps.
 // ---------------------------------------------------------------------------
+__device__ inline double pyth(double f, double g) {
+    const double r2 = fma(f, f, g * g);
+    return (r2 > 1e-290 && r2 < 1e290) ? sqrt(r2) : hypot(f, g);
+}
+
 template <int NT>
 __device__ bool ql_small(int n, double* d, double* e, double* rc, double* rs, double* Z, int* ctl) {
     const int tid = threadIdx.x;
@@ -292,49 +319,65 @@ __device__ bool ql_small(int n, double* d, double* e, double* rc, double* rs, do
     for (int l = 0; l < n; ++l) {
         int iters = 0;
         for (;;) {
-            if (tid == 0) {
-                int m = l;
-                while (m < n - 1 && fabs(e[m]) > SEPS * (fabs(d[m]) + fabs(d[m + 1]))) ++m;
-                ctl[0] = l;
-                ctl[1] = -1;
-                if (m != l) {
-                    if (++iters > 30) {
-                        ctl[3] = 1;
-                    } else {
-                        double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
-                        double r = hypot(g, 1.0);
-                        g = d[m] - d[l] + e[l] / (g + copysign(r, g));
-                        double s = 1.0, c = 1.0, p = 0.0;
-                        int lo = l;
-                        bool split = false;
-                        for (int i = m - 1; i >= l; --i) {
-                            const double f = s * e[i], b = c * e[i];
-                            r = hypot(f, g);
-                            e[i + 1] = r;
-                            if (r == 0.0) {
-                                d[i + 1] -= p;
-                                e[m] = 0.0;
-                                lo = i + 1;
-                                split = true;
-                                break;
+            if (tid < WAVE) {
+                int m = n - 1;
+                for (int base = l; base < n - 1; base += WAVE) {
+                    const int i = base + tid;
+                    const bool split = i >= n - 1 || !(fabs(e[i]) > SEPS * (fabs(d[i]) + fabs(d[i + 1])));
+                    const unsigned long long bal = __ballot(split);
+                    if (bal) {
+                        m = base + __builtin_ctzll(bal);
+                        break;
+                    }
+                }
+                if (tid == 0) {
+                    ctl[0] = l;
+                    ctl[1] = -1;
+                    if (m != l) {
+                        if (++iters > 30) {
+                            ctl[3] = 1;
+                        } else {
+                            double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
+                            double r = pyth(g, 1.0);
+                            g = d[m] - d[l] + e[l] / (g + copysign(r, g));
+                            double s = 1.0, c = 1.0, p = 0.0;
+                            int lo = l;
+                            bool split = false;
+                            double ei = e[m - 1], di = d[m - 1], di1 = d[m];
+                            for (int i = m - 1; i >= l; --i) {
+                                const double en = i > l ? e[i - 1] : 0.0, dn = i > l ? d[i - 1] : 0.0;
+                                const double f = s * ei, b = c * ei;
+                                r = pyth(f, g);
+                                e[i + 1] = r;
+                                if (r == 0.0) {
+                                    d[i + 1] = di1 - p;
+                                    e[m] = 0.0;
+                                    lo = i + 1;
+                                    split = true;
+                                    break;
+                                }
+                                const double rinv = 1.0 / r;
+                                s = f * rinv;
+                                c = g * rinv;
+                                g = di1 - p;
+                                r = (di - g) * s + 2.0 * c * b;
+                                p = s * r;
+                                d[i + 1] = g + p;
+                                g = c * r - b;
+                                rc[i] = c;
+                                rs[i] = s;
+                                ei = en;
+                                di1 = di;
+                                di = dn;
                             }
-                            s = f / r;
-                            c = g / r;
-                            g = d[i + 1] - p;
-                            r = (d[i] - g) * s + 2.0 * c * b;
-                            p = s * r;
-                            d[i + 1] = g + p;
-                            g = c * r - b;
-                            rc[i] = c;
-                            rs[i] = s;
+                            if (!split) {
+                                d[l] -= p;
+                                e[l] = g;
+                                e[m] = 0.0;
+                            }
+                            ctl[0] = lo;
+                            ctl[1] = m;
                         }
-                        if (!split) {
-                            d[l] -= p;
-                            e[l] = g;
-                            e[m] = 0.0;
-                        }
-                        ctl[0] = lo;
-                        ctl[1] = m;
                     }
                 }
             }
@@ -422,22 +465,29 @@ __device__ void solve_one(const SmallDesc& D, double* Z, Lds<T>& L, T (*dblk)[RB
     T* H = reinterpret_cast<T*>(D.H);
     T* S = reinterpret_cast<T*>(D.S);
     const long ldh = D.ldh, lds = D.lds;
+    const bool factor = !D.factored;
     int bad = 0;
     for (long x = tid; x < (long)n * n; x += NT) {
         const int j = (int)(x / n), i = (int)(x - (long)j * n);
         if (i <= j) {
-            const T a = H[IDX(i, j, ldh)], b = S[IDX(i, j, lds)];
-            if (!isfinite(realp(a)) || !isfinite(imagp(a)) || !isfinite(realp(b)) || !isfinite(imagp(b))) bad = 1;
+            const T a = H[IDX(i, j, ldh)];
+            if (!isfinite(realp(a)) || !isfinite(imagp(a))) bad = 1;
+            if (factor) {
+                const T b = S[IDX(i, j, lds)];
+                if (!isfinite(realp(b)) || !isfinite(imagp(b))) bad = 1;
+            }
         }
     }
     if (__syncthreads_or(bad)) {
         if (tid == 0) *D.info = GEVD_E_NONFINITE;
         return;
     }
-    const int minor = chol_small<T, NT>(S, lds, n, dblk, ctl);
-    if (minor) {
-        if (tid == 0) *D.info = minor;
-        return;
+    if (factor) {  // otherwise S keeps U and U^H from an earlier solve (fixed overlap)
+        const int minor = chol_small<T, NT>(S, lds, n, dblk, ctl);
+        if (minor) {
+            if (tid == 0) *D.info = minor;
+            return;
+        }
     }
     // full Hermitian H from its upper triangle
     for (long x = tid; x < (long)n * n; x += NT) {
@@ -501,8 +551,8 @@ __global__ __launch_bounds__(NT) void small_solve_kernel(const SmallDesc* desc, 
                                                          long zslot, int* counter) {
     extern __shared__ __align__(16) char dyn[];
     __shared__ T dblk[RB][RB + 1];
-    __shared__ T red[NT / WAVE + 1];
-    __shared__ double redd[NT / WAVE];
+    __shared__ T red[QMAX + 1];  // chunk sums, and the reflector scale in the last slot
+    __shared__ double redd[QMAX];
     __shared__ int ctl[4];
     __shared__ int prob;
     Lds<T> L;

@@ -21,6 +21,7 @@ struct SmallDesc {
     int* info;     // 0, j > 0 (S not positive definite at minor j) or GEVD_E_*
     long ldh, lds, ldc;
     int n, nev;
+    int factored;  // S already holds U / U^H from an earlier solve: skip the Cholesky
 };
 
 // Dynamic LDS bytes of one workgroup for orders up to nmax.

@@ -37,7 +37,10 @@ class Problem(ctypes.Structure):
     """gevd_problem of include/gevd.h."""
     _fields_ = [("dtype", ctypes.c_int), ("n", ctypes.c_int), ("nev", ctypes.c_int),
                 ("H", ctypes.c_void_p), ("ldh", ctypes.c_int), ("S", ctypes.c_void_p), ("lds", ctypes.c_int),
-                ("eval", ctypes.c_void_p), ("C", ctypes.c_void_p), ("ldc", ctypes.c_int)]
+                ("eval", ctypes.c_void_p), ("C", ctypes.c_void_p), ("ldc", ctypes.c_int), ("flags", ctypes.c_int)]
+
+
+PROBLEM_FACTORED = 1
 
 
 class GevdError(RuntimeError):
@@ -279,7 +282,7 @@ class Solver:
         return w, Z
 
     # --------------------------------------------------------- batched small
-    def _problems(self, items, outs):
+    def _problems(self, items, outs, factored=False):
         arr = (Problem * len(items))()
         keep = []
         for i, (H, S, nev) in enumerate(items):
@@ -295,27 +298,29 @@ class Solver:
                 w, C = outs[i]
             keep.append((w, C))
             arr[i] = Problem(_dtype_code(H), n, nev, H.data_ptr(), _ld(H, n, "H"), S.data_ptr(), _ld(S, n, "S"),
-                             w.data_ptr(), C.data_ptr(), _ld(C, n, "C"))
+                             w.data_ptr(), C.data_ptr(), _ld(C, n, "C"), PROBLEM_FACTORED if factored else 0)
         return arr, keep
 
-    def solve_batched(self, items, outs=None):
+    def solve_batched(self, items, outs=None, factored: bool = False):
         """Solve many small problems in fused persistent launches.
 
         items: sequence of (H, S, nev) with n <= 512 (H clobbered; S receives
         U in its upper and U^H in its strictly lower triangle).  outs: optional matching (eval, C)
-        buffers.  Returns (results, info): results[i] = (eval, C) and info[i]
-        the problem's status (0, j > 0 not positive definite at minor j, or an
-        E_* code); raises only for errors of the launch itself."""
-        arr, keep = self._problems(items, outs)
+        buffers.  factored: every S already holds its factor from an earlier
+        batched solve (the Cholesky is skipped).  Returns (results, info):
+        results[i] = (eval, C) and info[i] the problem's status (0, j > 0 not
+        positive definite at minor j, or an E_* code); raises only for errors
+        of the launch itself."""
+        arr, keep = self._problems(items, outs, factored)
         info = (ctypes.c_int * len(items))()
         self._stream()
         _check(load().gevd_solve_batched(self._h, len(items), arr, info), "gevd_solve_batched")
         return keep, list(info)
 
-    def batch(self, items, outs=None) -> "Batch":
+    def batch(self, items, outs=None, factored: bool = False) -> "Batch":
         """A reusable batch (descriptors uploaded, launches captured in a HIP
         graph) over fixed buffers; see Batch.run."""
-        arr, keep = self._problems(items, outs)
+        arr, keep = self._problems(items, outs, factored)
         b = ctypes.c_void_p()
         self._stream()
         _check(load().gevd_batch_create(self._h, len(items), arr, ctypes.byref(b)), "gevd_batch_create")

@@ -75,7 +75,14 @@ class StreamResult:
 
     def summary(self) -> dict:
         lat = np.array([r.latency for r in self.records]) if self.records else np.zeros(1)
+        by = {}
+        for name, sel in (("small", lambda r: r.batched), ("large", lambda r: not r.batched)):
+            ls = np.array([r.latency for r in self.records if sel(r)])
+            if ls.size:
+                by[name] = {"solves": int(ls.size), "p50_s": float(np.percentile(ls, 50)),
+                            "p99_s": float(np.percentile(ls, 99))}
         return {
+            "by_class": by,
             "solves": len(self.records),
             "solves_per_s": len(self.records) / self.makespan if self.makespan > 0 else 0.0,
             "p50_s": float(np.percentile(lat, 50)),
@@ -331,31 +338,58 @@ class GpuWorkers:
                 self.results[req.rid] = outs
 
     def run_batch(self, reqs: list[Request], on_solve, t0: float):
+        """Small requests together: the first SCF iteration factors every S
+        in the batched kernel; the later ones replay a captured batch that
+        reuses the factors (S fixed) with the iteration's H written into the
+        same buffers."""
         import torch
-
-        from . import gevd
 
         solver, stream = self._solver()
         with torch.cuda.stream(stream):
-            inputs = [request_inputs(r, self.device) for r in reqs]
-            submits = [r.arrival for r in reqs]
-            outs = {r.rid: [] for r in reqs}
-            its = max(r.iters for r in reqs)
-            for it in range(its):
-                live = [i for i, r in enumerate(reqs) if it < r.iters]
-                Hs = [scf_h(inputs[i][0], reqs[i], it) for i in live]
-                Ss = [inputs[i][1].clone() for i in live]
-                res = gevd.solve_batched(Hs, Ss, [reqs[i].k for i in live], solver=solver)
-                stream.synchronize()
-                done = time.perf_counter() - t0
-                for j, i in enumerate(live):
-                    on_solve(SolveRecord(reqs[i].rid, it, reqs[i].n, reqs[i].cplx, submits[i], done, batched=True))
-                    submits[i] = done
-                    if self.keep:
-                        outs[reqs[i].rid].append((res[j][0].cpu().numpy(), res[j][1].cpu().numpy()))
+            outs, submits = batched_scf(solver, reqs, t0, on_solve, self.keep, stream)
         if self.keep:
             with self.rlock:
                 self.results.update(outs)
+
+
+def batched_scf(solver, reqs: list[Request], t0: float, on_solve=None, keep: bool = True, stream=None):
+    """SCF iterations of a group of small requests on the batched path (the
+    current stream).  Returns ({rid: [(eval, C) per iteration]}, last submit
+    times)."""
+    import torch
+
+    inputs = [request_inputs(r, solver.device) for r in reqs]
+    Hb = [torch.empty_like(H0) for H0, _ in inputs]
+    Sb = [S.clone() for _, S in inputs]
+    items = [(Hb[i], Sb[i], r.k) for i, r in enumerate(reqs)]
+    outs = {r.rid: [] for r in reqs}
+    submits = [r.arrival for r in reqs]
+    its = max(r.iters for r in reqs)
+    graph = None
+    for it in range(its):
+        for i, r in enumerate(reqs):
+            Hb[i].copy_(scf_h(inputs[i][0], r, it))
+        if it == 0:
+            res, info = solver.solve_batched(items)
+        else:
+            if graph is None:
+                graph = solver.batch(items, outs=res, factored=True)
+            info = graph.run()
+        if any(info):
+            raise RuntimeError("batched solve failed: info %s" % info)
+        (stream or torch.cuda.current_stream()).synchronize()
+        done = time.perf_counter() - t0
+        for i, r in enumerate(reqs):
+            if it >= r.iters:
+                continue
+            if on_solve is not None:
+                on_solve(SolveRecord(r.rid, it, r.n, r.cplx, submits[i], done, batched=True))
+            submits[i] = done
+            if keep:
+                outs[r.rid].append((res[i][0].cpu().numpy(), res[i][1].cpu().numpy()))
+    if graph is not None:
+        graph.close()
+    return outs, submits
 
 
 def serve(requests: list[Request], device=None, budget_bytes: int | None = None, large_workers: int = 4,
@@ -376,23 +410,27 @@ def serve(requests: list[Request], device=None, budget_bytes: int | None = None,
     def workspace_of(r: Request) -> int:
         return gevd.workspace_bytes(torch.complex128 if r.cplx else torch.float64, r.n, r.k)
 
-    has_batched = hasattr(gevd, "solve_batched")
     sched = Scheduler(budget_bytes, large_workers, small_workers, small_n, workspace_of, workers.run_request,
-                      workers.run_batch if has_batched else None, batch=batch if has_batched else 1,
-                      batch_wait=batch_wait)
+                      workers.run_batch, batch=batch, batch_wait=batch_wait)
     res = sched.run(requests)
     res.results = workers.results
     return res
 
 
-def solve_alone(req: Request, device=None):
-    """The same request served by itself (fresh handle, default stream)."""
+def solve_alone(req: Request, device=None, small_n: int = 512):
+    """The same request served by itself on the route the server gives it
+    (a batch of one for n <= small_n, the resident path otherwise), with a
+    fresh handle on the default stream."""
     import torch
 
     from . import gevd
 
     device = torch.device(device or "cuda:0")
     solver = gevd.Solver(device)
+    if req.n <= small_n:
+        outs, _ = batched_scf(solver, [req], 0.0)
+        solver.close()
+        return outs[req.rid]
     H0, S = request_inputs(req, device)
     solver.set_overlap(S)
     outs = []
@@ -402,6 +440,74 @@ def solve_alone(req: Request, device=None):
         outs.append((w.cpu().numpy(), C.cpu().numpy()))
     solver.close()
     return outs
+
+
+def batched_throughput(count: int = 1024, iters: int = 5, seed: int = 4, small=(64, 512), frac_complex: float = 0.6,
+                       tune: bool = False, device=None) -> dict:
+    """Throughput of the batched path alone on `count` small requests of the
+    serving mix (n uniform in `small`, 60 % complex, lowest 30 %): the first
+    SCF iteration factors every S; the later ones replay the captured batch
+    with the factors reused.  Device time from the library's kernel
+    accounting (HIP events around each launch)."""
+    import torch
+
+    from . import gevd
+
+    device = torch.device(device or "cuda:0")
+    torch.cuda.set_device(device)
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for rid in range(count):
+        n = int(rng.integers(small[0], small[1] + 1))
+        reqs.append(Request(rid, bool(rng.random() < frac_complex), n, max(1, int(math.ceil(0.3 * n - 1e-9))), 0.0,
+                            seed=7_000_003 * seed + rid, iters=iters))
+    solver = gevd.Solver(device, kstats=True)
+    tuned = {}
+    if tune:
+        for dt in (torch.float64, torch.complex128):
+            for nb in (64, 128, 256, 512):
+                tuned["%s:%d" % ("z" if dt == torch.complex128 else "d", nb)] = solver.tune_batched(dt, nb, 512)
+    inputs = [request_inputs(r, device) for r in reqs]
+    Hb = [torch.empty_like(H0) for H0, _ in inputs]
+    Sb = [S.clone() for _, S in inputs]
+    items = [(Hb[i], Sb[i], r.k) for i, r in enumerate(reqs)]
+    for i, r in enumerate(reqs):
+        Hb[i].copy_(scf_h(inputs[i][0], r, 0))
+    torch.cuda.synchronize()
+    solver.reset_kernel_stats()
+    t1 = time.perf_counter()
+    res, info = solver.solve_batched(items)
+    first_wall = time.perf_counter() - t1
+    assert not any(info), info
+    st = solver.kernel_stats()["small"]
+    first = {"ms": st["ms"], "tflops": st["flops"] / (st["ms"] / 1e3) / 1e12}
+    graph = solver.batch(items, outs=res, factored=True)
+    solver.reset_kernel_stats()
+    walls = []
+    for it in range(1, iters):
+        for i, r in enumerate(reqs):
+            Hb[i].copy_(scf_h(inputs[i][0], r, it))
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        info = graph.run()
+        walls.append(time.perf_counter() - t1)
+        assert not any(info), info
+    st = solver.kernel_stats()["small"]
+    later = {"ms_per_iter": st["ms"] / max(1, iters - 1), "tflops": st["flops"] / (st["ms"] / 1e3) / 1e12}
+    graph.close()
+    shapes = {"%s:%d" % (tag, nb): solver.batch_shape(dt, nb) for dt, tag in ((torch.float64, "d"),
+                                                                             (torch.complex128, "z"))
+              for nb in (64, 128, 256, 512)}
+    solver.close()
+    return {"mode": "batched", "problems": count, "complex_fraction": frac_complex, "n_range": list(small),
+            "first_iteration": {"device_ms": round(first["ms"], 2), "wall_ms": round(first_wall * 1e3, 2),
+                                "solves_per_s": round(count / (first["ms"] / 1e3), 1),
+                                "tflops": round(first["tflops"], 3)},
+            "factored_iterations": {"device_ms": round(later["ms_per_iter"], 2),
+                                    "wall_ms": round(1e3 * float(np.median(walls)), 2) if walls else None,
+                                    "solves_per_s": round(count / (later["ms_per_iter"] / 1e3), 1),
+                                    "tflops": round(later["tflops"], 3)},
+            "shapes": shapes, "tuned": tuned}
 
 
 def main():
@@ -415,7 +521,12 @@ def main():
     ap.add_argument("--large-max", type=int, default=8192)
     ap.add_argument("--large-workers", type=int, default=4)
     ap.add_argument("--small-workers", type=int, default=2)
+    ap.add_argument("--mode", choices=("stream", "batched"), default="stream")
+    ap.add_argument("--tune", action="store_true", help="batched mode: run the shape tuner first")
     args = ap.parse_args()
+    if args.mode == "batched":
+        print(json.dumps(batched_throughput(args.requests, args.iters, tune=args.tune)), flush=True)
+        return
     reqs = poisson_stream(args.requests, args.rate, large=(1024, args.large_max), iters=args.iters)
     res = serve(reqs, large_workers=args.large_workers, small_workers=args.small_workers)
     out = res.summary()

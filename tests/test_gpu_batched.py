@@ -108,3 +108,23 @@ def test_tuner_and_shapes(gpu_lib, solver):
     assert np.abs(host(wv) - w_ref).max() / np.abs(w_ref).max() < 1e-10
     solver.set_batch_shape(torch.float64, 60, 0, 0)  # back to the default
     log(f"tuned shape for real n<=64: {t} lanes, {w} workgroups per CU")
+
+
+def test_result_independent_of_launch_shape(solver):
+    """Reductions inside the fused kernel run in a fixed order, so the launch
+    shape (lanes per workgroup, workgroups per CU) changes speed only."""
+    ps = [synth.pencil(n, c, 1e-6, 300 + n, 0.3) for n, c in ((100, False), (300, True), (480, False))]
+    outs = []
+    for threads, wg in ((64, 4), (256, 1), (512, 1)):
+        for dt in (torch.float64, torch.complex128):
+            for n in (64, 128, 256, 512):
+                solver.set_batch_shape(dt, n, threads, wg)
+        res, info = solver.solve_batched(_items(ps))
+        assert info == [0] * len(ps)
+        outs.append([(host(w), host(C)) for w, C in res])
+    for dt in (torch.float64, torch.complex128):
+        for n in (64, 128, 256, 512):
+            solver.set_batch_shape(dt, n, 0, 0)
+    for other in outs[1:]:
+        for (w0, C0), (w1, C1) in zip(outs[0], other):
+            assert np.array_equal(w0, w1) and np.array_equal(C0, C1)
