@@ -35,12 +35,42 @@ CONFIGS = {
 
 FP64_PEAK_TFLOPS = 78.6  # MI355X dense FP64 matrix peak (datasheet); the FP64 vector peak is the same
 # roofline bound of each kernel family
-FAMILY_BOUND = {"gemm": "mfma", "backchase": "mfma", "panel": "alu", "chase": "alu", "dc": "alu", "other": "alu"}
+FAMILY_BOUND = {"gemm": "mfma", "gemm32": "mfma", "backchase": "mfma", "panel": "alu", "chase": "alu", "dc": "alu",
+                "other": "alu", "small": "alu"}
 
 
 def nominal_flops(n: int, k: int, cplx: bool) -> float:
     f = 8.0 * n ** 3 / 3.0 + 5.0 * n * n * k
     return 4.0 * f if cplx else f
+
+
+def _norm2_est(M, iters: int = 30) -> float:
+    """2-norm of a Hermitian device matrix by power iteration."""
+    import torch
+
+    g = torch.Generator(device=M.device)
+    g.manual_seed(5)
+    x = torch.randn(M.shape[0], dtype=torch.float64, device=M.device, generator=g).to(M.dtype)
+    x = x / torch.linalg.vector_norm(x)
+    nrm = 0.0
+    for _ in range(iters):
+        y = M @ x
+        nrm = float(torch.linalg.vector_norm(y))
+        x = y / nrm
+    return nrm
+
+
+def sample_eta(H, S, w, C, k, count: int = 8, norms=None):
+    """Backward error eta_i = ||H c - w S c|| / ((||H|| + |w| ||S||) ||c||)
+    for `count` wanted pairs spread over the k (device products, FP64)."""
+    import torch
+
+    nh, ns = norms if norms is not None else (_norm2_est(H), _norm2_est(S))
+    idx = sorted(set(int(round(i * (k - 1) / max(count - 1, 1))) for i in range(count)))
+    Cs = C[:, idx]
+    R = H @ Cs - (S @ Cs) * w[idx].to(C.dtype)[None, :]
+    eta = torch.linalg.vector_norm(R, dim=0) / ((nh + w[idx].abs() * ns) * torch.linalg.vector_norm(Cs, dim=0))
+    return float(eta.max()), (nh, ns)
 
 
 def cpu_baseline(cplx: bool, n_full: int, k_frac: float, sigma_min: float, budget_s: float = 20.0):
@@ -79,6 +109,7 @@ def main():
     ap.add_argument("--config", default="c2", choices=sorted(CONFIGS))
     ap.add_argument("--band", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32+refine comparison")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (--gpus %d requested)" % args.gpus,
@@ -171,6 +202,38 @@ def main():
                        "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(ach / FP64_PEAK_TFLOPS, 4),
                        "traffic": None, "launches_per_step": g["launches"] // args.steps,
                        "avg_launch_ms": round(g["ms"] / g["launches"], 4)}
+    if not args.no_fp32:
+        # the same workload in the reduced-precision form, compared with the
+        # FP64 result of the last timed step on the same input
+        w64 = w.clone()
+        C64 = C.clone()
+        eta64, norms = sample_eta(H0, S0, w64, C64, k)
+        solver.set_precision("fp32+refine", 2)
+        for i in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        per32 = []
+        t32 = time.perf_counter()
+        for i in range(args.steps):
+            t1 = time.perf_counter()
+            step()
+            torch.cuda.synchronize()
+            per32.append(time.perf_counter() - t1)
+            print("# fp32+refine step %d: %.3f s" % (i, per32[-1]), file=sys.stderr, flush=True)
+        tot32 = time.perf_counter() - t32
+        eta32, _ = sample_eta(H0, S0, w, C, k, norms=norms)
+        nrm = float(w64[:k].abs().max())
+        sp = sorted(per32)
+        out["fp32_refine"] = {
+            "ms_per_step": round(1e3 * tot32 / args.steps, 2),
+            "value": round(fl / (tot32 / args.steps) / 1e12, 3),
+            "p50_s": round(sp[len(sp) // 2], 4), "p99_s": round(sp[-1], 4),
+            "speedup_vs_fp64": round((total / args.steps) / (tot32 / args.steps), 3),
+            "eig_err_vs_fp64_normwise": float((w[:k] - w64[:k]).abs().max()) / nrm,
+            "eta_sample_max": eta32, "eta_sample_max_fp64": eta64,
+            "refine_sweeps": 2,
+        }
+        solver.set_precision("fp64")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cplx, n, frac, smin)
     print(json.dumps(out), flush=True)

@@ -57,6 +57,25 @@ extern "C" {
 #define GEVD_OPT_TIMING 2   /* 1: record per-phase device times (events) */
 #define GEVD_OPT_LEAF 3     /* divide-and-conquer leaf size (0 = auto) */
 #define GEVD_OPT_KSTATS 4   /* 1: time kernel families with HIP events (see gevd_get_kernel_stats) */
+#define GEVD_OPT_PRECISION 5 /* GEVD_PREC_FP64 (default) or GEVD_PREC_FP32_REFINE */
+#define GEVD_OPT_REFINE 6   /* refinement sweeps of the reduced-precision form (0..10, default 2) */
+
+/* Precision forms (GEVD_OPT_PRECISION) of gevd_solve, gevd_solve_resident
+ * and gevd_eigh.  FP32_REFINE: the products of the full -> band reduction
+ * and of the stage-1 back-transformation run on the FP32 matrix cores
+ * (operands rounded to FP32, FP32 accumulation; A itself stays FP64); the
+ * Cholesky, inversion, the two products forming A, band -> tridiagonal, the
+ * divide-and-conquer solve and the bulge-reflector back-transformation stay
+ * FP64; then the nev wanted pairs are refined in FP64 against A by the
+ * Ogita-Aishima correction restricted to their subspace (G = X^H X,
+ * M = X^H A X, X <- X + X E), GEVD_OPT_REFINE sweeps.  eval[0..nev) holds the
+ * refined values (ascending); eval[nev..n) the values of the reduced-
+ * precision stages.  The refinement cannot restore components that the
+ * FP32 stages lost outside the wanted subspace: for an ill-conditioned S
+ * (large ||A||, eigenvalues clustered relative to it) the result stays near
+ * FP32 accuracy. */
+#define GEVD_PREC_FP64 0
+#define GEVD_PREC_FP32_REFINE 1
 
 /* Kernel families reported by gevd_get_kernel_stats. */
 #define GEVD_K_GEMM 0       /* MFMA matrix products (all shapes, both scalar types) */
@@ -66,7 +85,8 @@ extern "C" {
 #define GEVD_K_DC 4         /* divide-and-conquer (leaves, merge steps; merge products count as GEMM) */
 #define GEVD_K_OTHER 5      /* everything else (Cholesky diagonal blocks, T factors, copies) */
 #define GEVD_K_SMALL 6      /* batched small problems (one fused persistent launch per group) */
-#define GEVD_NKFAM 7
+#define GEVD_K_GEMM32 7     /* matrix products of the reduced-precision form (FP32 matrix cores) */
+#define GEVD_NKFAM 8
 
 /* Phases reported by gevd_get_timings (milliseconds, last solve). */
 #define GEVD_PH_CHOLESKY 0  /* S = U^H U */

@@ -11,6 +11,8 @@ struct gevd_ctx {
     int band_opt = 0;
     int leaf_opt = 0;
     int timing = 0;
+    int prec = 0;          // GEVD_OPT_PRECISION
+    int refine_iters = 2;  // GEVD_OPT_REFINE
     char* ws = nullptr;  // workspace (device)
     size_t ws_bytes = 0;
     int* flags = nullptr;  // small device status area

@@ -41,10 +41,12 @@ struct EighWs {
     T* bb_work;      // back_band scratch
     double* Zr;      // real eigenvectors from D&C (n x nev)
     char* dc_ws;     // D&C scratch
+    T* acopy;        // reduced-precision form: FP64 copy of A for the refinement
+    T* rf_work;      // refinement scratch
 };
 
 template <typename T>
-size_t carve_eigh(char* base, int n, int nev, int b, int leaf, EighWs<T>* out) {
+size_t carve_eigh(char* base, int n, int nev, int b, int leaf, EighWs<T>* out, int prec = 0) {
     Carve c{base};
     EighWs<T> w;
     const int np = count_panels(n, b);
@@ -73,6 +75,8 @@ size_t carve_eigh(char* base, int n, int nev, int b, int leaf, EighWs<T>* out) {
     w.bb_work = c.take<T>(back_band_ws_elems<T>(n, nev, b));
     w.Zr = c.take<double>((size_t)n * nev);
     w.dc_ws = c.take<char>(stedc_ws_bytes(n, nev, leaf));
+    w.acopy = prec ? c.take<T>((size_t)n * n) : nullptr;
+    w.rf_work = prec ? c.take<T>(refine_ws_elems<T>(n, nev)) : nullptr;
     if (out) *out = w;
     return c.off;
 }
@@ -114,8 +118,8 @@ size_t band_ws_bytes(int n, int b) {
 }
 
 template <typename T>
-size_t eigh_ws_bytes(int n, int nev, int b, int leaf) {
-    return carve_eigh<T>(nullptr, n, nev, b, leaf, nullptr) + 256;
+size_t eigh_ws_bytes(int n, int nev, int b, int leaf, int prec) {
+    return carve_eigh<T>(nullptr, n, nev, b, leaf, nullptr, prec) + 256;
 }
 
 template <typename T>
@@ -139,9 +143,13 @@ int tridiag_run(const StageCtx& c, int n, T* A, long lda, double* d, double* e, 
 template <typename T>
 int eigh_run(const StageCtx& c, int n, int nev, T* A, long lda, double* eval, T* Z, long ldz, char* ws) {
     EighWs<T> w;
-    carve_eigh<T>(ws, n, nev, c.b, c.leaf, &w);
-    int rc = he2hb<T>(c, n, A, lda, w.R1, w.Bw, w.ldw, w.he_work);
-    if (rc) return rc;
+    carve_eigh<T>(ws, n, nev, c.b, c.leaf, &w, c.prec);
+    int rc = 0;
+    if (c.prec && (rc = copy_matrix<T>(c.st, n, n, A, lda, w.acopy, n))) return rc;
+    {
+        Fp32Gemm f32(c.prec != 0);
+        if ((rc = he2hb<T>(c, n, A, lda, w.R1, w.Bw, w.ldw, w.he_work))) return rc;
+    }
     c.phase(GEVD_PH_TRIDIAG);
     if ((rc = hb2st<T>(c, n, w.Bw, w.ldw, w.R2, w.d, w.e, w.sync_area))) return rc;
     c.phase(GEVD_PH_SOLVE);
@@ -152,14 +160,19 @@ int eigh_run(const StageCtx& c, int n, int nev, T* A, long lda, double* eval, T*
     if (rc) return rc;
     if ((rc = back_chase<T>(c, w.R2, nev, Z, ldz))) return rc;
     c.phase(GEVD_PH_BACK1);
-    return back_band<T>(c, w.R1, nev, Z, ldz, w.bb_work);
+    {
+        Fp32Gemm f32(c.prec != 0);
+        if ((rc = back_band<T>(c, w.R1, nev, Z, ldz, w.bb_work))) return rc;
+    }
+    if (c.prec) rc = refine<T>(c, n, nev, w.acopy, n, Z, ldz, eval, w.rf_work, c.refine_iters);
+    return rc;
 }
 
 #define INST(T)                                                                              \
     template size_t back_band_ws_elems<T>(int, int, int);                                    \
     template int back_band<T>(const StageCtx&, const BandRefl<T>&, int, T*, long, T*);       \
     template size_t band_ws_bytes<T>(int, int);                                              \
-    template size_t eigh_ws_bytes<T>(int, int, int, int);                                    \
+    template size_t eigh_ws_bytes<T>(int, int, int, int, int);                               \
     template int band_run<T>(const StageCtx&, int, T*, long, T*, long, char*);               \
     template int tridiag_run<T>(const StageCtx&, int, T*, long, double*, double*, char*);    \
     template int eigh_run<T>(const StageCtx&, int, int, T*, long, double*, T*, long, char*);

@@ -16,8 +16,14 @@
 // store instruction writes 128-byte column segments of the column-major C.
 // Complex products use four real MFMAs per complex k-step (re*re - im*im,
 // re*im + im*re) on separately staged real/imaginary tiles.
+//
+// Reduced-precision form: inside a Fp32Gemm scope the operands are rounded
+// to FP32 when staged into LDS and the products run on the FP32 matrix
+// cores (v_mfma_f32_16x16x4_f32, FP32 accumulation, twice the FP64 rate);
+// the result is widened and combined with alpha / beta in FP64.
 #include <algorithm>
 #include <cstdlib>
+#include <type_traits>
 
 #include "kernels.hpp"
 
@@ -25,8 +31,24 @@ namespace gevd {
 namespace {
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
+typedef float flt4 __attribute__((ext_vector_type(4)));
 
 constexpr int BK = 16, NT = 256;
+
+// Accumulator of a 16x16 MFMA block and the MFMA itself, by compute type.
+template <typename CT> struct Acc;
+template <> struct Acc<double> {
+    typedef dbl4 type;
+    __device__ static inline dbl4 mma(double b, double a, dbl4 c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(b, a, c, 0, 0, 0);
+    }
+};
+template <> struct Acc<float> {
+    typedef flt4 type;
+    __device__ static inline flt4 mma(float b, float a, flt4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(b, a, c, 0, 0, 0);
+    }
+};
 
 template <typename T>
 struct GemmP {
@@ -74,15 +96,16 @@ __device__ inline T load_opB(const GemmP<T>& p, const T* B, int l, int j, int ke
 
 // Workgroup tile BM x BN = (2 WM) x (2 WN): 4 waves in a 2 x 2 layout, each
 // wave owns WM x WN as (WM/16) x (WN/16) MFMA blocks.
-template <typename T, int OPA, int OPB, int WM, int WN>
+template <typename T, typename CT, int OPA, int OPB, int WM, int WN>
 __global__ __launch_bounds__(NT) void gemm_kernel(GemmP<T> p) {
+    typedef typename Acc<CT>::type AccT;
     constexpr bool CX = is_cplx<T>::value;
     constexpr int NC = CX ? 2 : 1;
     constexpr int BM = 2 * WM, BN = 2 * WN;
     constexpr int FA = WM / 16, FB = WN / 16;  // MFMA blocks per wave
     constexpr int LA = BM * BK / NT, LB = BN * BK / NT;  // elements loaded per thread
-    __shared__ double sA[NC][2][BK][BM + 4];
-    __shared__ double sB[NC][2][BK][BN + 4];
+    __shared__ CT sA[NC][2][BK][BM + 4];
+    __shared__ CT sB[NC][2][BK][BN + 4];
 
     const int ti = blockIdx.x % p.tiles_m, tj = blockIdx.x / p.tiles_m;
     // triangle modes skip tiles whose every element lies on the other side
@@ -110,13 +133,13 @@ __global__ __launch_bounds__(NT) void gemm_kernel(GemmP<T> p) {
     const int lane = t % WAVE, w = t / WAVE;
     const int wm = w % 2, wn = w / 2;
 
-    dbl4 accR[FA][FB], accI[FA][FB];
+    AccT accR[FA][FB], accI[FA][FB];
 #pragma unroll
     for (int a = 0; a < FA; ++a)
 #pragma unroll
         for (int b = 0; b < FB; ++b) {
-            accR[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
-            accI[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
+            accR[a][b] = AccT{0, 0, 0, 0};
+            accI[a][b] = AccT{0, 0, 0, 0};
         }
 
     // The next operand slab is loaded into registers while the MFMAs read the
@@ -154,8 +177,8 @@ __global__ __launch_bounds__(NT) void gemm_kernel(GemmP<T> p) {
             int ii, ll;
             if (OPA == OP_N && !herm_up) { ii = e % BM; ll = e / BM; }
             else { ii = e / BK; ll = e % BK; }
-            sA[0][buf][ll][ii] = realp(ra[r]);
-            if (CX) sA[NC - 1][buf][ll][ii] = imagp(ra[r]);
+            sA[0][buf][ll][ii] = (CT)realp(ra[r]);
+            if (CX) sA[NC - 1][buf][ll][ii] = (CT)imagp(ra[r]);
         }
 #pragma unroll
         for (int r = 0; r < LB; ++r) {
@@ -163,15 +186,15 @@ __global__ __launch_bounds__(NT) void gemm_kernel(GemmP<T> p) {
             int jj, ll;
             if (OPB == OP_N) { ll = e % BK; jj = e / BK; }
             else { jj = e % BN; ll = e / BN; }
-            sB[0][buf][ll][jj] = realp(rb[r]);
-            if (CX) sB[NC - 1][buf][ll][jj] = imagp(rb[r]);
+            sB[0][buf][ll][jj] = (CT)realp(rb[r]);
+            if (CX) sB[NC - 1][buf][ll][jj] = (CT)imagp(rb[r]);
         }
     };
     auto compute = [&](int buf) {
 #pragma unroll
         for (int kk = 0; kk < BK / 4; ++kk) {
             const int kr = kk * 4 + lane / 16;
-            double aR[FA], bR[FB], aI[FA], bI[FB];
+            CT aR[FA], bR[FB], aI[FA], bI[FB];
 #pragma unroll
             for (int q = 0; q < FA; ++q) {
                 aR[q] = sA[0][buf][kr][wm * WM + q * 16 + lane % 16];
@@ -188,23 +211,23 @@ __global__ __launch_bounds__(NT) void gemm_kernel(GemmP<T> p) {
             for (int qa = 0; qa < FA; ++qa)
 #pragma unroll
                 for (int qb = 0; qb < FB; ++qb)
-                    accR[qa][qb] = __builtin_amdgcn_mfma_f64_16x16x4f64(bR[qb], aR[qa], accR[qa][qb], 0, 0, 0);
+                    accR[qa][qb] = Acc<CT>::mma(bR[qb], aR[qa], accR[qa][qb]);
             if (CX) {
 #pragma unroll
                 for (int qa = 0; qa < FA; ++qa)
 #pragma unroll
                     for (int qb = 0; qb < FB; ++qb)
-                        accI[qa][qb] = __builtin_amdgcn_mfma_f64_16x16x4f64(bI[qb], aR[qa], accI[qa][qb], 0, 0, 0);
+                        accI[qa][qb] = Acc<CT>::mma(bI[qb], aR[qa], accI[qa][qb]);
 #pragma unroll
                 for (int qa = 0; qa < FA; ++qa)
 #pragma unroll
                     for (int qb = 0; qb < FB; ++qb)
-                        accR[qa][qb] = __builtin_amdgcn_mfma_f64_16x16x4f64(-bI[qb], aI[qa], accR[qa][qb], 0, 0, 0);
+                        accR[qa][qb] = Acc<CT>::mma(-bI[qb], aI[qa], accR[qa][qb]);
 #pragma unroll
                 for (int qa = 0; qa < FA; ++qa)
 #pragma unroll
                     for (int qb = 0; qb < FB; ++qb)
-                        accI[qa][qb] = __builtin_amdgcn_mfma_f64_16x16x4f64(bR[qb], aI[qa], accI[qa][qb], 0, 0, 0);
+                        accI[qa][qb] = Acc<CT>::mma(bR[qb], aI[qa], accI[qa][qb]);
             }
         }
     };
@@ -236,7 +259,9 @@ __global__ __launch_bounds__(NT) void gemm_kernel(GemmP<T> p) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int row = i0 + wm * WM + qa * 16 + lane % 16;
-                int col = j0 + wn * WN + qb * 16 + 4 * r + lane / 16;
+                // f32 16x16x4 differs: register r of lane l holds D[4 (l/16) + r][l%16]
+                int col = j0 + wn * WN + qb * 16 + (std::is_same<CT, float>::value ? 4 * (lane / 16) + r
+                                                                                   : 4 * r + lane / 16);
                 if (row >= p.m || col >= p.n) continue;
                 if (strict_up && row > col) continue;
                 if (strict_lo && row < col) continue;
@@ -245,8 +270,8 @@ __global__ __launch_bounds__(NT) void gemm_kernel(GemmP<T> p) {
                     if (col < 0) continue;
                 }
                 T v;
-                if constexpr (CX) v = zdouble{accR[qa][qb][r], accI[qa][qb][r]};
-                else v = accR[qa][qb][r];
+                if constexpr (CX) v = zdouble{(double)accR[qa][qb][r], (double)accI[qa][qb][r]};
+                else v = (double)accR[qa][qb][r];
                 if (p.splitk > 1) {
                     p.work[(size_t)blockIdx.z * p.m * p.n + IDX(row, col, p.m)] = v;
                 } else {
@@ -274,14 +299,20 @@ __global__ void splitk_reduce(int m, int n, int splits, const T* work, T alpha, 
     C[IDX(row, col, ldc)] = out;
 }
 
+template <typename T, typename CT, int OPA, int OPB>
+void launch_c(hipStream_t st, const GemmP<T>& p, dim3 grid, int cfg) {
+    switch (cfg) {
+        case 1: hipLaunchKernelGGL((gemm_kernel<T, CT, OPA, OPB, 64, 32>), grid, dim3(NT), 0, st, p); break;
+        case 2: hipLaunchKernelGGL((gemm_kernel<T, CT, OPA, OPB, 32, 64>), grid, dim3(NT), 0, st, p); break;
+        case 3: hipLaunchKernelGGL((gemm_kernel<T, CT, OPA, OPB, 64, 64>), grid, dim3(NT), 0, st, p); break;
+        default: hipLaunchKernelGGL((gemm_kernel<T, CT, OPA, OPB, 32, 32>), grid, dim3(NT), 0, st, p); break;
+    }
+}
+
 template <typename T, int OPA, int OPB>
 void launch_t(hipStream_t st, const GemmP<T>& p, dim3 grid, int cfg) {
-    switch (cfg) {
-        case 1: hipLaunchKernelGGL((gemm_kernel<T, OPA, OPB, 64, 32>), grid, dim3(NT), 0, st, p); break;
-        case 2: hipLaunchKernelGGL((gemm_kernel<T, OPA, OPB, 32, 64>), grid, dim3(NT), 0, st, p); break;
-        case 3: hipLaunchKernelGGL((gemm_kernel<T, OPA, OPB, 64, 64>), grid, dim3(NT), 0, st, p); break;
-        default: hipLaunchKernelGGL((gemm_kernel<T, OPA, OPB, 32, 32>), grid, dim3(NT), 0, st, p); break;
-    }
+    if (g_gemm_fp32) launch_c<T, float, OPA, OPB>(st, p, grid, cfg);
+    else launch_c<T, double, OPA, OPB>(st, p, grid, cfg);
 }
 
 template <typename T, int OPA>
@@ -343,6 +374,8 @@ double algorithmic_flops(int m, int n, int k, int kmode, int tmode, bool cx) {
 
 }  // namespace
 
+thread_local bool g_gemm_fp32 = false;
+
 template <typename T>
 int gemm(hipStream_t st, int opA, int opB, int m, int n, int k, T alpha, const T* A, long lda, const T* B,
          long ldb, T beta, T* C, long ldc, int kmode, int tmode, Batch batch, int splitk, T* work, const int* amap,
@@ -369,7 +402,7 @@ int gemm(hipStream_t st, int opA, int opB, int m, int n, int k, T alpha, const T
     p.splitk = splitk; p.work = work;
     p.amap = amap; p.cmap = cmap;
     dim3 grid(p.tiles_m * tiles_n, batch.count, splitk);
-    KProbe probe(st, GEVD_K_GEMM,
+    KProbe probe(st, g_gemm_fp32 ? GEVD_K_GEMM32 : GEVD_K_GEMM,
                  g_kstats ? batch.count * algorithmic_flops(m, n, k, kmode, tmode, is_cplx<T>::value) : 0.0);
     if (opA == OP_N) launch_b<T, OP_N>(st, opB, p, grid, cfg);
     else if (opA == OP_T) launch_b<T, OP_T>(st, opB, p, grid, cfg);

@@ -151,13 +151,15 @@ size_t plan_solve(const gevd_ctx* h, int n, int nev) {
     Bump b(nullptr);
     b.take<T>((size_t)n * n);  // Uinv
     size_t rest = std::max({plan_cholesky<T>(n), plan_invert<T>(n), plan_reduce<T>(n),
-                            eigh_ws_bytes<T>(n, nev, pick_band(h, n), h->leaf_opt)});
+                            eigh_ws_bytes<T>(n, nev, pick_band(h, n), h->leaf_opt, h->prec)});
     return b.off + 256 + rest + (size_t)n * nev * sizeof(T) + 256;
 }
 
 template <typename T>
 int do_eigh(gevd_ctx* h, int n, int nev, T* A, int lda, double* eval, T* Z, int ldz, char* ws, bool timed) {
     StageCtx sc{h->stream, h->flags + F_NOCONV, h->flags + F_HANG, pick_band(h, n), h->leaf_opt};
+    sc.prec = h->prec;
+    sc.refine_iters = h->refine_iters;
     if (timed) {
         sc.mark = [](void* p, int ph) { mark((gevd_ctx*)p, ph); };
         sc.mark_arg = h;
@@ -332,6 +334,14 @@ int gevd_set_option(gevd_handle h, int option, int value) {
         case GEVD_OPT_KSTATS:
             h->kstats_on = value ? 1 : 0;
             return 0;
+        case GEVD_OPT_PRECISION:
+            if (value != GEVD_PREC_FP64 && value != GEVD_PREC_FP32_REFINE) return -3;
+            h->prec = value;
+            return 0;
+        case GEVD_OPT_REFINE:
+            if (value < 0 || value > 10) return -3;
+            h->refine_iters = value;
+            return 0;
         default:
             return -2;
     }
@@ -493,8 +503,8 @@ int gevd_eigh(gevd_handle h, int dtype, int n, int nev, void* A, int lda, double
     if (hipSetDevice(h->device) != hipSuccess) return GEVD_E_HIP;
     KScope kscope(h);
     int b = pick_band(h, n);
-    size_t need = dtype == GEVD_REAL ? eigh_ws_bytes<double>(n, nev, b, h->leaf_opt)
-                                     : eigh_ws_bytes<zdouble>(n, nev, b, h->leaf_opt);
+    size_t need = dtype == GEVD_REAL ? eigh_ws_bytes<double>(n, nev, b, h->leaf_opt, h->prec)
+                                     : eigh_ws_bytes<zdouble>(n, nev, b, h->leaf_opt, h->prec);
     int rc = ensure_ws(h, need);
     if (rc) return rc;
     if ((rc = clear_flags(h))) return rc;

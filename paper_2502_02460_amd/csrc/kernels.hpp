@@ -27,6 +27,15 @@ enum TMode {
     T_LOWER_STRICT = 4,  // lower tiles, and only elements i >= j stored
 };
 
+// Products issued on this thread while set run on the FP32 matrix cores
+// (operands rounded to FP32, FP32 accumulation); see Fp32Gemm.
+extern thread_local bool g_gemm_fp32;
+struct Fp32Gemm {
+    bool prev;
+    explicit Fp32Gemm(bool on) : prev(g_gemm_fp32) { g_gemm_fp32 = on; }
+    ~Fp32Gemm() { g_gemm_fp32 = prev; }
+};
+
 struct Batch {
     int count = 1;
     long long sA = 0, sB = 0, sC = 0;  // element strides between batch members

@@ -24,6 +24,12 @@
 namespace gevd {
 namespace {
 
+// Phase hooks for an external profiling build; empty here.
+#ifndef SMALL_MARK
+#define SMALL_MARK_INIT() ((void)0)
+#define SMALL_MARK(phase) ((void)0)
+#endif
+
 constexpr double SEPS = 2.220446049250313e-16;
 constexpr int RB = 8;                    // register block of the Cholesky and substitutions
 constexpr int QMAX = SMALL_MAX / WAVE;   // rows per lane when a wave owns a column
@@ -465,6 +471,7 @@ __device__ void solve_one(const SmallDesc& D, double* Z, Lds<T>& L, T (*dblk)[RB
     T* H = reinterpret_cast<T*>(D.H);
     T* S = reinterpret_cast<T*>(D.S);
     const long ldh = D.ldh, lds = D.lds;
+    SMALL_MARK_INIT();
     const bool factor = !D.factored;
     int bad = 0;
     for (long x = tid; x < (long)n * n; x += NT) {
@@ -482,6 +489,7 @@ __device__ void solve_one(const SmallDesc& D, double* Z, Lds<T>& L, T (*dblk)[RB
         if (tid == 0) *D.info = GEVD_E_NONFINITE;
         return;
     }
+    SMALL_MARK(0);
     if (factor) {  // otherwise S keeps U and U^H from an earlier solve (fixed overlap)
         const int minor = chol_small<T, NT>(S, lds, n, dblk, ctl);
         if (minor) {
@@ -489,6 +497,7 @@ __device__ void solve_one(const SmallDesc& D, double* Z, Lds<T>& L, T (*dblk)[RB
             return;
         }
     }
+    SMALL_MARK(1);
     // full Hermitian H from its upper triangle
     for (long x = tid; x < (long)n * n; x += NT) {
         const int j = (int)(x / n), i = (int)(x - (long)j * n);
@@ -498,6 +507,7 @@ __device__ void solve_one(const SmallDesc& D, double* Z, Lds<T>& L, T (*dblk)[RB
     __syncthreads();
     row_solve<T, NT>(H, ldh, S, lds, n);  // X = H U^{-1}
     __syncthreads();
+    SMALL_MARK(2);
     for (long x = tid; x < (long)n * n; x += NT) {  // X <- X^H
         const int j = (int)(x / n), i = (int)(x - (long)j * n);
         if (i < j) {
@@ -522,11 +532,14 @@ __device__ void solve_one(const SmallDesc& D, double* Z, Lds<T>& L, T (*dblk)[RB
         }
     }
     __syncthreads();
+    SMALL_MARK(3);
     tridiag_small<T, NT>(H, ldh, n, L, red, redd);
+    SMALL_MARK(4);
     if (!ql_small<NT>(n, L.d, L.e, L.rc, L.rs, Z, ctl)) {
         if (tid == 0) *D.info = GEVD_E_NOCONV;
         return;
     }
+    SMALL_MARK(5);
     // ascending order by rank (ties broken by index); perm starts as the
     // identity so that every entry is a valid column even for unordered input
     for (int i = tid; i < n; i += NT) L.perm[i] = i;
@@ -542,7 +555,10 @@ __device__ void solve_one(const SmallDesc& D, double* Z, Lds<T>& L, T (*dblk)[RB
     }
     __syncthreads();
     for (int i = tid; i < n; i += NT) D.eval[i] = L.d[L.perm[i]];
+    SMALL_MARK(6);
     back_small<T, NT>(D, H, S, Z, L);
+    __syncthreads();
+    SMALL_MARK(7);
     if (tid == 0) *D.info = 0;
 }
 

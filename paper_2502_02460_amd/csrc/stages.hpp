@@ -12,6 +12,11 @@ struct StageCtx {
     int leaf;     // divide-and-conquer leaf size (0 = default)
     void (*mark)(void*, int) = nullptr;
     void* mark_arg = nullptr;
+    // 1: reduced-precision form (full -> band and stage-1 back-transformation
+    // products on the FP32 matrix cores, then FP64 refinement of the wanted
+    // pairs against a copy of A)
+    int prec = 0;
+    int refine_iters = 2;
     void phase(int p) const {
         if (mark) mark(mark_arg, p);
     }
@@ -50,7 +55,7 @@ constexpr int chase_group() {
 template <typename T>
 size_t band_ws_bytes(int n, int b);
 template <typename T>
-size_t eigh_ws_bytes(int n, int nev, int b, int leaf);
+size_t eigh_ws_bytes(int n, int nev, int b, int leaf, int prec = 0);
 size_t stedc_ws_bytes(int n, int nev, int leaf);
 
 // Full Hermitian A (clobbered) -> band in lower band storage (Bd, ldb).
@@ -79,5 +84,10 @@ template <typename T>
 int back_band(const StageCtx& c, const BandRefl<T>& R, int nev, T* Z, long ldz, T* work);
 template <typename T>
 size_t back_band_ws_elems(int n, int nev, int b);
+// FP64 refinement of k approximate eigenpairs (refine.hip).
+template <typename T>
+size_t refine_ws_elems(int n, int k);
+template <typename T>
+int refine(const StageCtx& c, int n, int k, const T* A, long lda, T* X, long ldx, double* eval, T* work, int iters);
 
 }  // namespace gevd

@@ -23,8 +23,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 SO_PATH = os.path.join(_HERE, "libgevd.so")
 
 GEVD_REAL, GEVD_COMPLEX = 0, 1
-OPT_BAND, OPT_TIMING, OPT_LEAF, OPT_KSTATS = 1, 2, 3, 4
-KFAMILIES = ("gemm", "panel", "chase", "backchase", "dc", "other", "small")
+OPT_BAND, OPT_TIMING, OPT_LEAF, OPT_KSTATS, OPT_PRECISION, OPT_REFINE = 1, 2, 3, 4, 5, 6
+PREC_FP64, PREC_FP32_REFINE = 0, 1
+KFAMILIES = ("gemm", "panel", "chase", "backchase", "dc", "other", "small", "gemm32")
 SMALL_MAX = 512
 PHASES = ("cholesky", "invert", "multiply", "band", "tridiag", "solve", "back2", "back1", "mult")
 E_NONFINITE, E_NOCONV, E_NOMEM, E_HIP, E_STATE, E_HANG = -1001, -1002, -1003, -1004, -1005, -1006
@@ -141,7 +142,8 @@ class Solver:
     """A library handle bound to one device; keeps its workspace between
     calls.  Work goes to the current torch stream of that device."""
 
-    def __init__(self, device=None, band: int = 0, leaf: int = 0, timing: bool = False, kstats: bool = False):
+    def __init__(self, device=None, band: int = 0, leaf: int = 0, timing: bool = False, kstats: bool = False,
+                 precision: str = "fp64", refine: int = 2):
         L = load()
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else
                                    torch.device(device).index or 0)
@@ -156,6 +158,16 @@ class Solver:
             _check(L.gevd_set_option(h, OPT_TIMING, 1), "gevd_set_option")
         if kstats:
             _check(L.gevd_set_option(h, OPT_KSTATS, 1), "gevd_set_option")
+        self.set_precision(precision, refine)
+
+    def set_precision(self, precision: str = "fp64", refine: int = 2):
+        """'fp64', or 'fp32+refine': full -> band and stage-1 back-transform
+        products on the FP32 matrix cores, then `refine` FP64 refinement
+        sweeps of the wanted pairs (see include/gevd.h)."""
+        code = {"fp64": PREC_FP64, "fp32+refine": PREC_FP32_REFINE}[precision]
+        _check(load().gevd_set_option(self._h, OPT_PRECISION, code), "gevd_set_option")
+        _check(load().gevd_set_option(self._h, OPT_REFINE, int(refine)), "gevd_set_option")
+        self.precision = precision
 
     def close(self):
         if getattr(self, "_h", None):
