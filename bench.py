@@ -44,6 +44,32 @@ def nominal_flops(n: int, k: int, cplx: bool) -> float:
     return 4.0 * f if cplx else f
 
 
+def plain_inputs(n: int, cplx: bool, frac: float, seed: int, dev):
+    """H = (G + G^H)/2 with G Gaussian, S = I + (R + R^H)/(4n): elementwise
+    device ops only."""
+    import torch
+
+    g = torch.Generator(device=dev)
+    g.manual_seed(seed)
+    dt = torch.complex128 if cplx else torch.float64
+
+    def draw():
+        x = torch.randn(n, n, dtype=torch.float64, device=dev, generator=g)
+        if cplx:
+            x = torch.complex(x, torch.randn(n, n, dtype=torch.float64, device=dev, generator=g))
+        return x
+
+    G = draw()
+    H = (0.5 * (G + G.mT.conj())).to(dt)
+    del G
+    R = draw()
+    S = ((R + R.mT.conj()) / (4.0 * n)).to(dt)
+    del R
+    S.diagonal().add_(1.0)
+    k = max(1, int(math.ceil(frac * n - 1e-9)))
+    return H.mT.contiguous().mT, S.mT.contiguous().mT, k
+
+
 def _norm2_est(M, iters: int = 30) -> float:
     """2-norm of a Hermitian device matrix by power iteration."""
     import torch
@@ -110,6 +136,9 @@ def main():
     ap.add_argument("--band", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32+refine comparison")
+    ap.add_argument("--inputs", choices=("paper", "plain"), default="paper",
+                    help="plain: H random Hermitian, S = I + R/(4n), drawn with elementwise device ops only "
+                         "(no library QR or BLAS calls; for profiler passes that cannot instrument those)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (--gpus %d requested)" % args.gpus,
@@ -124,7 +153,10 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     t0 = time.time()
-    H0, S0, k, _ = synth.pencil_torch(n, cplx, smin, seed, frac, dev)
+    if args.inputs == "paper":
+        H0, S0, k, _ = synth.pencil_torch(n, cplx, smin, seed, frac, dev)
+    else:
+        H0, S0, k = plain_inputs(n, cplx, frac, seed, dev)
     torch.cuda.synchronize()
     print("# inputs drawn in %.1f s (n=%d k=%d %s)" % (time.time() - t0, n, k, "complex" if cplx else "real"),
           file=sys.stderr, flush=True)
@@ -183,7 +215,8 @@ def main():
         "vs_baseline": None,
         "dtype": "c128" if cplx else "f64",
         "data": "synthetic",
-        "config": {"workload": label, "n": n, "nev": k, "complex": cplx, "sigma_min": smin,
+        "config": {"workload": label if args.inputs == "paper" else label + " (plain inputs)", "n": n, "nev": k,
+                   "complex": cplx, "sigma_min": smin,
                    "band": solver.band_width(n, H0.dtype)},
         "p50_s": round(p50, 4),
         "p99_s": round(p99, 4),

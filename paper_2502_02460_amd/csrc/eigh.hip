@@ -27,7 +27,7 @@ int count_panels(int n, int b) {
     return np;
 }
 
-constexpr int SKB = 4;  // split of the long inner dimension in the stage-1 back-transform
+constexpr int SKB = 8;  // split of the long inner dimension in the stage-1 back-transform
 
 template <typename T>
 struct EighWs {

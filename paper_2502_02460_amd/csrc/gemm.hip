@@ -305,6 +305,8 @@ void launch_c(hipStream_t st, const GemmP<T>& p, dim3 grid, int cfg) {
         case 1: hipLaunchKernelGGL((gemm_kernel<T, CT, OPA, OPB, 64, 32>), grid, dim3(NT), 0, st, p); break;
         case 2: hipLaunchKernelGGL((gemm_kernel<T, CT, OPA, OPB, 32, 64>), grid, dim3(NT), 0, st, p); break;
         case 3: hipLaunchKernelGGL((gemm_kernel<T, CT, OPA, OPB, 64, 64>), grid, dim3(NT), 0, st, p); break;
+        case 4: hipLaunchKernelGGL((gemm_kernel<T, CT, OPA, OPB, 32, 16>), grid, dim3(NT), 0, st, p); break;
+        case 5: hipLaunchKernelGGL((gemm_kernel<T, CT, OPA, OPB, 16, 32>), grid, dim3(NT), 0, st, p); break;
         default: hipLaunchKernelGGL((gemm_kernel<T, CT, OPA, OPB, 32, 32>), grid, dim3(NT), 0, st, p); break;
     }
 }
@@ -323,19 +325,23 @@ void launch_b(hipStream_t st, int opB, const GemmP<T>& p, dim3 grid, int cfg) {
 }
 
 // Workgroup tile for a product: 0 = 64x64, 1 = 128x64, 2 = 64x128,
-// 3 = 128x128.  GEVD_GEMM_TILE forces one (for measurements).
+// 3 = 128x128, 4 = 64x32 (outputs at most 32 columns wide), 5 = 32x64 (at
+// most 32 rows).  GEVD_GEMM_TILE forces one (for measurements).
+constexpr int TILE_BM[6] = {64, 128, 64, 128, 64, 32};
+constexpr int TILE_BN[6] = {64, 64, 128, 128, 32, 64};
 int g_tile_override = -2;  // -2: not read yet, -1: none
 int pick_tile(int m, int n, int k, bool cx) {
     if (g_tile_override == -2) {
         const char* e = getenv("GEVD_GEMM_TILE");
         g_tile_override = e ? atoi(e) : -1;
     }
-    if (g_tile_override >= 0 && g_tile_override <= 3) return (cx && g_tile_override == 3) ? 1 : g_tile_override;
-    // measured on gfx950: 64 x 64 is fastest for every shape the solver uses
-    (void)m;
-    (void)n;
+    if (g_tile_override >= 0 && g_tile_override <= 5) return (cx && g_tile_override == 3) ? 1 : g_tile_override;
     (void)k;
     (void)cx;
+    // measured on gfx950: 64 x 64 is fastest for the solver's square-ish
+    // shapes; a skinny output would leave half of each 64-wide tile idle
+    if (n <= 32 && m > 32) return 4;
+    if (m <= 32 && n > 32) return 5;
     return 0;
 }
 
@@ -393,7 +399,7 @@ int gemm(hipStream_t st, int opA, int opB, int m, int n, int k, T alpha, const T
     p.alpha = alpha; p.beta = beta;
     p.kmode = kmode; p.tmode = tmode;
     const int cfg = pick_tile(m, n, k, is_cplx<T>::value);
-    const int bm = (cfg & 1) ? 128 : 64, bn = (cfg & 2) ? 128 : 64;
+    const int bm = TILE_BM[cfg], bn = TILE_BN[cfg];
     p.bm = bm;
     p.bn = bn;
     p.tiles_m = (m + bm - 1) / bm;
