@@ -166,10 +166,13 @@ def main():
     C = torch.empty((k, n), dtype=H0.dtype, device=dev).mT
     w = torch.empty(n, dtype=torch.float64, device=dev)
 
+    work_stream = torch.cuda.Stream(device=dev)  # a non-default stream (default priority)
+
     def step():
-        H.copy_(H0)
-        S.copy_(S0)
-        solver.solve(H, S, k, C=C, eval_out=w)
+        with torch.cuda.stream(work_stream):
+            H.copy_(H0)
+            S.copy_(S0)
+            solver.solve(H, S, k, C=C, eval_out=w)
 
     for i in range(args.warmup):
         t1 = time.time()

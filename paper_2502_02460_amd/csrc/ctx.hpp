@@ -30,4 +30,7 @@ struct gevd_ctx {
     int bthreads[2][gevd::SMALL_NBUCKET] = {};
     int bwgpcu[2][gevd::SMALL_NBUCKET] = {};
     int ncu = 0;
+    // second stream and events for overlapped stages (created on first use)
+    hipStream_t aux = nullptr;
+    hipEvent_t aux_fork = nullptr, aux_join = nullptr;
 };

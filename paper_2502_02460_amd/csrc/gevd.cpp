@@ -81,6 +81,34 @@ struct KScope {
     ~KScope() { g_kstats = nullptr; }
 };
 
+// The second stream of overlapped stages (default priority, ordered against
+// the handle's stream by events only); left null if it cannot be made.
+// Its work may not use the last few CUs, which stay free for the latency-
+// bound kernels running on the handle's stream at the same time.
+void attach_aux(gevd_ctx* h, StageCtx& sc) {
+    if (!h->aux) {
+        int ncu = 0;
+        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h->device) != hipSuccess) ncu = 0;
+        constexpr int RESERVE = 16;
+        bool made = false;
+        if (ncu > 4 * RESERVE && ncu <= 32 * 16) {
+            uint32_t mask[16] = {};
+            for (int cu = 0; cu < ncu - RESERVE; ++cu) mask[cu / 32] |= 1u << (cu % 32);
+            made = hipExtStreamCreateWithCUMask(&h->aux, (uint32_t)((ncu + 31) / 32), mask) == hipSuccess;
+        }
+        if (!made) (void)hipGetLastError();
+        if ((!made && hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking) != hipSuccess) ||
+            hipEventCreateWithFlags(&h->aux_fork, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&h->aux_join, hipEventDisableTiming) != hipSuccess) {
+            (void)hipGetLastError();
+            return;
+        }
+    }
+    sc.aux = h->aux;
+    sc.fork = h->aux_fork;
+    sc.join = h->aux_join;
+}
+
 int pick_band(const gevd_ctx* h, int n) {
     int b = h->band_opt > 0 ? h->band_opt : 32;
     if (n <= 2 * b) b = std::max(1, std::min(b, n / 2));
@@ -158,6 +186,7 @@ size_t plan_solve(const gevd_ctx* h, int n, int nev) {
 template <typename T>
 int do_eigh(gevd_ctx* h, int n, int nev, T* A, int lda, double* eval, T* Z, int ldz, char* ws, bool timed) {
     StageCtx sc{h->stream, h->flags + F_NOCONV, h->flags + F_HANG, pick_band(h, n), h->leaf_opt};
+    attach_aux(h, sc);
     sc.prec = h->prec;
     sc.refine_iters = h->refine_iters;
     if (timed) {
@@ -295,6 +324,10 @@ int gevd_destroy(gevd_handle h) {
     if (!h) return -1;
     (void)hipSetDevice(h->device);
     (void)hipStreamSynchronize(h->stream);
+    if (h->aux) (void)hipStreamSynchronize(h->aux);
+    if (h->aux_fork) (void)hipEventDestroy(h->aux_fork);
+    if (h->aux_join) (void)hipEventDestroy(h->aux_join);
+    if (h->aux) (void)hipStreamDestroy(h->aux);
     if (h->ws) (void)hipFree(h->ws);
     if (h->uinv) (void)hipFree(h->uinv);
     if (h->flags) (void)hipFree(h->flags);
@@ -544,6 +577,7 @@ int gevd_band(gevd_handle h, int dtype, int n, void* A, int lda, void* Bd, int l
     int rc = ensure_ws(h, need);
     if (rc) return rc;
     StageCtx sc{h->stream, h->flags + F_NOCONV, h->flags + F_HANG, b, h->leaf_opt};
+    attach_aux(h, sc);
     return dtype == GEVD_REAL ? band_run<double>(sc, n, (double*)A, lda, (double*)Bd, ldb, h->ws)
                               : band_run<zdouble>(sc, n, (zdouble*)A, lda, (zdouble*)Bd, ldb, h->ws);
 }
@@ -565,6 +599,7 @@ int gevd_tridiagonalize(gevd_handle h, int dtype, int n, void* A, int lda, doubl
     if (rc) return rc;
     if ((rc = clear_flags(h))) return rc;
     StageCtx sc{h->stream, h->flags + F_NOCONV, h->flags + F_HANG, b, h->leaf_opt};
+    attach_aux(h, sc);
     rc = dtype == GEVD_REAL ? tridiag_run<double>(sc, n, (double*)A, lda, d, e, h->ws)
                             : tridiag_run<zdouble>(sc, n, (zdouble*)A, lda, d, e, h->ws);
     if (rc) return rc;
@@ -589,6 +624,7 @@ int gevd_stedc(gevd_handle h, int n, int nev, const double* d, const double* e, 
     if (rc) return rc;
     if ((rc = clear_flags(h))) return rc;
     StageCtx sc{h->stream, h->flags + F_NOCONV, h->flags + F_HANG, 0, h->leaf_opt};
+    attach_aux(h, sc);
     rc = stedc_run(sc, n, nev, d, e, eval, Z, ldz, h->ws);
     if (rc) return rc;
     int fl[NFLAGS];

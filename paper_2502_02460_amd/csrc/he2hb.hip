@@ -271,6 +271,8 @@ int he2hb(const StageCtx& c, int n, T* A, long lda, BandRefl<T>& R, T* Bd, long 
     const T one = from_real<T>(1.0), mone = from_real<T>(-1.0), zero = zero_of<T>();
     const T mhalf = from_real<T>(-0.5);
     int rc;
+    const bool look = c.aux != nullptr && c.fork != nullptr && c.join != nullptr;
+    bool pending = false;
     // the panel scratch counter must start at zero
     if ((rc = set_zero<T>(st, (int)((sizeof(PanelScratch<T>) + sizeof(T) - 1) / sizeof(T)), 1, (T*)w.ps, 1)))
         return rc;
@@ -305,6 +307,10 @@ int he2hb(const StageCtx& c, int n, T* A, long lda, BandRefl<T>& R, T* Bd, long 
         T* Wb = w.LR;                  // columns [0, b): W
         T* Vb = w.LR + (size_t)m * b;  // columns [b, 2b): V
         T* W2 = w.LR + (size_t)2 * m * b;  // columns [2b, 3b): W again
+        if (pending) {  // the previous trailing update on the second stream
+            GEVD_HIP(hipStreamWaitEvent(st, c.join, 0));
+            pending = false;
+        }
         // A22 is kept only in its lower triangle: Y = A22 V reads it as Hermitian
         if ((rc = gemm<T>(st, OP_N, OP_N, m, b, m, one, A22, lda, Vp, m, zero, w.Y, m, K_A_HERM_LOWER, T_ALL,
                           Batch(), m >= 2048 ? SK : 1, w.skY)))
@@ -317,10 +323,26 @@ int he2hb(const StageCtx& c, int n, T* A, long lda, BandRefl<T>& R, T* Bd, long 
         if ((rc = gemm<T>(st, OP_N, OP_N, m, b, b, mhalf, Vp, m, w.M2, b, one, Wb, m))) return rc;  // W
         if ((rc = copy_matrix<T>(st, m, b, Wb, m, W2, m))) return rc;
         if ((rc = copy_matrix<T>(st, m, b, Vp, m, Vb, m))) return rc;
-        // lower tiles of A22 -= W V^H + V W^H (the upper triangle is never read again)
-        if ((rc = gemm<T>(st, OP_N, OP_C, m, m, 2 * b, mone, w.LR, m, Vb, m, one, A22, lda, K_FULL, T_LOWER_TILES)))
-            return rc;
+        // lower tiles of A22 -= W V^H + V W^H (the upper triangle is never read
+        // again).  With a second stream: the next panel's b columns first,
+        // then the rest on the second stream while the next panel is
+        // factored; the next product with A22 waits for it.
+        if (!look || m <= b) {
+            if ((rc = gemm<T>(st, OP_N, OP_C, m, m, 2 * b, mone, w.LR, m, Vb, m, one, A22, lda, K_FULL,
+                              T_LOWER_TILES)))
+                return rc;
+        } else {
+            if ((rc = gemm<T>(st, OP_N, OP_C, m, b, 2 * b, mone, w.LR, m, Vb, m, one, A22, lda))) return rc;
+            GEVD_HIP(hipEventRecord(c.fork, st));
+            GEVD_HIP(hipStreamWaitEvent(c.aux, c.fork, 0));
+            if ((rc = gemm<T>(c.aux, OP_N, OP_C, m - b, m - b, 2 * b, mone, w.LR + b, m, Vb + b, m, one,
+                              A22 + IDX(b, b, lda), lda, K_FULL, T_LOWER_TILES)))
+                return rc;
+            GEVD_HIP(hipEventRecord(c.join, c.aux));
+            pending = true;
+        }
     }
+    if (pending) GEVD_HIP(hipStreamWaitEvent(st, c.join, 0));
     const long long tot = (long long)ldb * n;
     hipLaunchKernelGGL(extract_band<T>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, n, b, np, (const T*)A,
                        lda, Bd, ldb);

@@ -17,6 +17,11 @@ struct StageCtx {
     // pairs against a copy of A)
     int prec = 0;
     int refine_iters = 2;
+    // optional second stream and two events (owned by the handle): the
+    // full -> band reduction runs each trailing update beside the next
+    // panel's factorization
+    hipStream_t aux = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
     void phase(int p) const {
         if (mark) mark(mark_arg, p);
     }
