@@ -44,6 +44,26 @@ def nominal_flops(n: int, k: int, cplx: bool) -> float:
     return 4.0 * f if cplx else f
 
 
+def measured_traffic(config: str, family: str):
+    """HBM bytes per launch of a kernel family from the committed PMC
+    summary (profiles/), or None when there is none for this workload or the
+    kernel source changed since the counters were taken."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "%s_family_%s_traffic.json" % (family, config))
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    src = os.path.join(ROOT, rec["source"])
+    if not os.path.exists(src):
+        return None
+    with open(src, "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != rec["source_sha256"]:
+            return None
+    return rec["hbm_bytes_per_launch"]
+
+
 def plain_inputs(n: int, cplx: bool, frac: float, seed: int, dev):
     """H = (G + G^H)/2 with G Gaussian, S = I + (R + R^H)/(4n): elementwise
     device ops only."""
@@ -236,7 +256,7 @@ def main():
     ach = g["flops"] / (g["ms"] / 1e3) / 1e12 if g["ms"] > 0 else 0.0
     out["roofline"] = {"kernel": dom, "bound": FAMILY_BOUND[dom], "achieved": round(ach, 3),
                        "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(ach / FP64_PEAK_TFLOPS, 4),
-                       "traffic": None, "launches_per_step": g["launches"] // args.steps,
+                       "traffic": measured_traffic(args.config, dom), "launches_per_step": g["launches"] // args.steps,
                        "avg_launch_ms": round(g["ms"] / g["launches"], 4)}
     if not args.no_fp32:
         # the same workload in the reduced-precision form, compared with the
