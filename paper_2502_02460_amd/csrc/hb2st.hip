@@ -25,8 +25,10 @@ namespace {
 
 constexpr int HT = 256;
 constexpr int MAXB = 64;
-constexpr long long SPIN_LIMIT = 200000000LL;
-constexpr int LB = 16;  // independent loads per lane per batch
+// A wait gives up after this much device time (wall clock at 100 MHz):
+// far beyond any legitimate wait, so only a broken invariant reaches it.
+constexpr unsigned long long WAIT_LIMIT_TICKS = 120ull * 100000000ull;
+constexpr int LB = 32;  // independent loads per lane per batch (b = 32: one batch)
 
 __device__ inline int ntasks(int n, int b, int sw) { return (n - 1 - sw + b - 1) / b; }
 
@@ -90,14 +92,24 @@ __global__ __launch_bounds__(64) void hb2st_kernel(int n, int b, T* Bw, long ldw
             if (sw > 0) {
                 if (lane == 0) {
                     const int need = min(t + 2, ntasks(n, b, sw - 1));
-                    long long spins = 0;
-                    // relaxed polling; one acquire fence once it is satisfied
+                    unsigned spins = 0;
+                    unsigned long long t_start = 0;
+                    // Relaxed polling, with an acquire every 64 polls: the L2
+                    // of this XCD is not coherent with the writer's, and a
+                    // relaxed load may keep hitting a stale line there until
+                    // an acquire invalidates it.  One acquire fence follows
+                    // once the wait is satisfied.
                     while (__hip_atomic_load(&progress[sw - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
-                        if (++spins > SPIN_LIMIT ||
-                            __hip_atomic_load(hang, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
-                            atomicOr(hang, 1);
-                            stop = 1;
-                            break;
+                        if ((++spins & 63u) == 0) {
+                            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                            const unsigned long long now = wall_clock64();
+                            if (t_start == 0) t_start = now;
+                            if (now - t_start > WAIT_LIMIT_TICKS ||
+                                __hip_atomic_load(hang, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                                atomicOr(hang, 1);
+                                stop = 1;
+                                break;
+                            }
                         }
                         __builtin_amdgcn_s_sleep(1);
                     }
@@ -218,8 +230,13 @@ __global__ __launch_bounds__(64) void hb2st_kernel(int n, int b, T* Bw, long ldw
             if (lane == 0) ptau = tau;
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // this wave's band stores, device-wide
             __syncthreads();
-            if (lane == 0)
+            if (lane == 0) {
                 __hip_atomic_store(&progress[sw], t + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                // A release orders the earlier stores before the counter; it
+                // does not push the counter itself out of this XCD's L2, so
+                // a waiter on another XCD could see it late.  Write it back.
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            }
         }
     }
 #undef EL_

@@ -33,6 +33,7 @@ namespace {
 constexpr double SEPS = 2.220446049250313e-16;
 constexpr int RB = 8;                    // register block of the Cholesky and substitutions
 constexpr int QMAX = SMALL_MAX / WAVE;   // rows per lane when a wave owns a column
+constexpr int ZC = 8;                    // entries per chunk of a row sweep (loads in flight)
 
 template <typename T>
 struct Lds {
@@ -267,13 +268,24 @@ __device__ void tridiag_small(T* A, long lda, int n, Lds<T>& L, T* red, double* 
         for (int i = o + tid; i < n; i += NT) {
             T acc = zero_of<T>();
             const T vi = pending ? v[i - j] : zero_of<T>(), wi = pending ? w[i - j] : zero_of<T>();
-            for (int c = o; c < n; ++c) {
-                T h = A[IDX(i, c, lda)];
-                if (pending) {
-                    h -= vi * conjg(w[c - j]) + wi * conjg(v[c - j]);
-                    A[IDX(i, c, lda)] = h;
+            for (int c0 = o; c0 < n; c0 += ZC) {  // chunks: loads in flight together
+                const int cnt = min(ZC, n - c0);
+                T h[ZC];
+#pragma unroll
+                for (int q = 0; q < ZC; ++q) h[q] = q < cnt ? A[IDX(i, c0 + q, lda)] : zero_of<T>();
+#pragma unroll
+                for (int q = 0; q < ZC; ++q) {
+                    if (q < cnt) {
+                        const int c = c0 + q;
+                        if (pending) h[q] -= vi * conjg(w[c - j]) + wi * conjg(v[c - j]);
+                        if (live) acc += h[q] * v2[c - o];
+                    }
                 }
-                if (live) acc += h * v2[c - o];
+                if (pending) {
+#pragma unroll
+                    for (int q = 0; q < ZC; ++q)
+                        if (q < cnt) A[IDX(i, c0 + q, lda)] = h[q];
+                }
             }
             y2[i - o] = tau * acc;
         }
@@ -387,19 +399,36 @@ __device__ bool ql_small(int n, double* d, double* e, double* rc, double* rs, do
                     }
                 }
             }
+            SMALL_MARK(8);
             __syncthreads();
             const int lo = ctl[0], m = ctl[1];
             if (m < 0) break;
+            // rows of Z, ZC entries per chunk: all loads of a chunk are issued
+            // before any of its stores, so they overlap in flight
             for (int k = tid; k < n; k += NT) {
                 double carry = Z[IDX(k, m, n)];
-                for (int i = m - 1; i >= lo; --i) {
-                    const double a = Z[IDX(k, i, n)];
-                    Z[IDX(k, i + 1, n)] = rs[i] * a + rc[i] * carry;
-                    carry = rc[i] * a - rs[i] * carry;
+                for (int i = m - 1; i >= lo; i -= ZC) {
+                    const int cnt = min(ZC, i - lo + 1);
+                    double a[ZC];
+#pragma unroll
+                    for (int q = 0; q < ZC; ++q) a[q] = q < cnt ? Z[IDX(k, i - q, n)] : 0.0;
+#pragma unroll
+                    for (int q = 0; q < ZC; ++q) {
+                        if (q < cnt) {
+                            const double c = rc[i - q], sn = rs[i - q];
+                            const double up = sn * a[q] + c * carry;
+                            carry = c * a[q] - sn * carry;
+                            a[q] = up;  // new entry of column i - q + 1
+                        }
+                    }
+#pragma unroll
+                    for (int q = 0; q < ZC; ++q)
+                        if (q < cnt) Z[IDX(k, i - q + 1, n)] = a[q];
                 }
                 Z[IDX(k, lo, n)] = carry;
             }
             __syncthreads();
+            SMALL_MARK(9);
         }
         if (ctl[3]) return false;
     }

@@ -72,6 +72,7 @@ class StreamResult:
     deferred: int = 0  # admissions postponed for memory
     peak_bytes: int = 0
     results: dict = field(default_factory=dict)  # rid -> list of (eval, C) per iteration (if kept)
+    errors: list = field(default_factory=list)   # (request ids, message) of failed work
 
     def summary(self) -> dict:
         lat = np.array([r.latency for r in self.records]) if self.records else np.zeros(1)
@@ -91,6 +92,7 @@ class StreamResult:
             "makespan_s": self.makespan,
             "deferred_admissions": self.deferred,
             "peak_admitted_bytes": self.peak_bytes,
+            "errors": len(self.errors),
         }
 
 
@@ -180,6 +182,9 @@ class Scheduler:
                         self.batch_executor(batch_reqs, on_solve, t0)
                     else:
                         self.executor(batch_reqs[0], on_solve, t0)
+                except Exception as exc:  # reported in the result, not lost with the thread
+                    with self.lock:
+                        self.result.errors.append(([r.rid for r in batch_reqs], repr(exc)))
                 finally:
                     finish(cost, cls, len(batch_reqs))
 
@@ -392,7 +397,7 @@ def batched_scf(solver, reqs: list[Request], t0: float, on_solve=None, keep: boo
     return outs, submits
 
 
-def serve(requests: list[Request], device=None, budget_bytes: int | None = None, large_workers: int = 4,
+def serve(requests: list[Request], device=None, budget_bytes: int | None = None, large_workers: int = 2,
           small_workers: int = 2, small_n: int = 512, batch: int = 8, batch_wait: float = 0.02,
           keep_results: bool = False) -> StreamResult:
     """Serve a request stream on one GPU; returns per-solve records."""
@@ -519,7 +524,7 @@ def main():
     ap.add_argument("--rate", type=float, default=200.0)
     ap.add_argument("--iters", type=int, default=5)
     ap.add_argument("--large-max", type=int, default=8192)
-    ap.add_argument("--large-workers", type=int, default=4)
+    ap.add_argument("--large-workers", type=int, default=2)
     ap.add_argument("--small-workers", type=int, default=2)
     ap.add_argument("--mode", choices=("stream", "batched"), default="stream")
     ap.add_argument("--tune", action="store_true", help="batched mode: run the shape tuner first")
@@ -530,7 +535,8 @@ def main():
     reqs = poisson_stream(args.requests, args.rate, large=(1024, args.large_max), iters=args.iters)
     res = serve(reqs, large_workers=args.large_workers, small_workers=args.small_workers)
     out = res.summary()
-    out.update({"requests": args.requests, "rate_per_s": args.rate, "iters": args.iters})
+    out.update({"requests": args.requests, "rate_per_s": args.rate, "iters": args.iters,
+                "error_messages": [m for _, m in res.errors][:4]})
     print(json.dumps(out), flush=True)
 
 

@@ -35,6 +35,7 @@ def test_mix_equals_alone(gpu_lib):
     res = serve.serve(reqs, keep_results=True, large_workers=2, small_workers=2, batch=4, batch_wait=0.01)
     summ = res.summary()
     log(f"served: {summ}")
+    assert not res.errors, res.errors
     assert summ["solves"] == sum(r.iters for r in reqs)
     assert summ["p99_s"] >= summ["p50_s"] > 0
     for r in reqs:

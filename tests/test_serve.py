@@ -92,3 +92,22 @@ def test_admission_defers_when_memory_is_short():
     first = sorted(res.records, key=lambda x: x.done)
     starts = sorted(reqs, key=lambda r: r.arrival)
     assert first[0].rid in (starts[0].rid, starts[1].rid)
+
+
+def test_worker_failures_are_reported():
+    reqs = serve.poisson_stream(12, 400.0, seed=9, large=(600, 900), iters=2)
+    run_request, run_batch = fake_device()
+
+    def failing(r, on_solve, t0):
+        if r.rid % 3 == 0:
+            raise RuntimeError("device error for %d" % r.rid)
+        run_request(r, on_solve, t0)
+
+    sched = serve.Scheduler(1 << 40, large_workers=2, small_workers=1, small_n=512, workspace_of=lambda r: 0,
+                            executor=failing, batch_executor=run_batch, batch=4, batch_wait=0.01)
+    res = sched.run(reqs)
+    bad = sorted(rid for rids, _ in res.errors for rid in rids)
+    assert bad == sorted(r.rid for r in reqs if r.n > 512 and r.rid % 3 == 0)
+    assert res.summary()["errors"] == len(bad)
+    ok = [r for r in reqs if r.rid not in bad]
+    assert len(res.records) == sum(r.iters for r in ok)
