@@ -397,10 +397,43 @@ __global__ __launch_bounds__(256) void back_chase_kernel(int n, int b, int nsw, 
             t = 0;
         }
     };
+    // The rows a group adds to the window are also fetched one group ahead
+    // (within a sweep block; the window's jump back to the top at the next
+    // block reads rows this workgroup may still hold, so those load in place).
+    constexpr int ZPT = MAXB * CT / 256;
+    T zpre[ZPT];
+    int pre_a = -1, pre_b = -1;
+    auto prefetch_rows = [&](int ra, int rb) {
+        const int nr = rb - ra;
+#pragma unroll
+        for (int k = 0; k < ZPT; ++k) {
+            const int e = tid + 256 * k;
+            zpre[k] = zero_of<T>();
+            if (e < nr * CT) {
+                const int r = ra + e % nr, c = e / nr;
+                if (c < ncol) zpre[k] = Z[IDX(r, c0 + c, ldz)];
+            }
+        }
+        pre_a = ra;
+        pre_b = rb;
+    };
+    auto commit_rows = [&]() {
+        const int nr = pre_b - pre_a;
+#pragma unroll
+        for (int k = 0; k < ZPT; ++k) {
+            const int e = tid + 256 * k;
+            if (e < nr * CT) {
+                const int r = pre_a + e % nr, c = e / nr;
+                zr[0][r & (RING - 1)][c] = realp(zpre[k]);
+                if (CX) zr[NC - 1][r & (RING - 1)][c] = imagp(zpre[k]);
+            }
+        }
+    };
     if (nblk > 0) fetch(nblk - 1, 0);
     for (int S = nblk - 1; S >= 0; --S) {
         const int s0 = S * NBS, s1 = min(nsw, s0 + NBS);
         int lo = -1, hi = -1;
+        pre_a = pre_b = -1;
         for (int t = 0;; ++t) {
             const int wr0 = s0 + 1 + t * b;
             if (wr0 >= n) break;
@@ -409,7 +442,11 @@ __global__ __launch_bounds__(256) void back_chase_kernel(int n, int b, int nsw, 
             if (hi > lo) store_rows(lo, min(hi, wr0));
             const int la = (hi > wr0) ? hi : wr0;
             __syncthreads();
-            if (wr1 > la) load_rows(la, wr1);
+            if (wr1 > la) {
+                if (pre_a == la && pre_b == wr1) commit_rows();
+                else load_rows(la, wr1);
+            }
+            pre_a = pre_b = -1;
             lo = wr0;
             hi = wr1;
             // this group's reflectors and T (fetched during the previous group)
@@ -432,6 +469,10 @@ __global__ __launch_bounds__(256) void back_chase_kernel(int n, int b, int nsw, 
                 int Sn = S, tn = t;
                 next_group(Sn, tn);
                 if (Sn >= 0) fetch(Sn, tn);
+                if (Sn == S) {  // next group of this block: rows [wr1, next wr1)
+                    const int nw1 = min(n, s1 + (t + 1) * b + b);
+                    if (nw1 > wr1 && nw1 - wr1 <= MAXB) prefetch_rows(wr1, nw1);
+                }
             }
             const int base = wr0;
             // ---- W = V^H Z: block jb of NBS/16, inner range split in P parts
