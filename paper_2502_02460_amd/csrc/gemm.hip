@@ -94,6 +94,33 @@ __device__ inline T load_opB(const GemmP<T>& p, const T* B, int l, int j, int ke
 }
 
 
+// Output tile of a workgroup.  Workgroups are dispatched to the 8 XCDs
+// round-robin (block b on XCD b % 8), each XCD with its own L2: blocks are
+// renumbered so that every XCD gets a contiguous range of tiles, and inside
+// it tiles go in groups of GM tile rows, so the workgroups resident on one
+// XCD at a time cover a compact block of C and share their A and B panels.
+// Products whose tiles differ in work (one triangle of tiles computed, or a
+// triangular operand clipping the inner range) keep the plain column-major
+// order: contiguous ranges would load some XCDs far more than others.
+constexpr int NXCD = 8, GM = 8;
+__device__ inline void tile_of(int bid, int nblocks, int tiles_m, bool swizzle, int& ti, int& tj) {
+    if (!swizzle) {
+        ti = bid % tiles_m;
+        tj = bid / tiles_m;
+        return;
+    }
+    const int per = nblocks / NXCD;
+    int l = bid;
+    if (bid < per * NXCD) l = (bid % NXCD) * per + bid / NXCD;
+    const int tiles_n = nblocks / tiles_m;
+    const int in_group = GM * tiles_n;
+    const int first = (l / in_group) * GM;
+    const int gm = min(tiles_m - first, GM);
+    const int r = l % in_group;
+    ti = first + r % gm;
+    tj = r / gm;
+}
+
 // Workgroup tile BM x BN = (2 WM) x (2 WN): 4 waves in a 2 x 2 layout, each
 // wave owns WM x WN as (WM/16) x (WN/16) MFMA blocks.
 template <typename T, typename CT, int OPA, int OPB, int WM, int WN>
@@ -107,7 +134,9 @@ __global__ __launch_bounds__(NT) void gemm_kernel(GemmP<T> p) {
     __shared__ CT sA[NC][2][BK][BM + 4];
     __shared__ CT sB[NC][2][BK][BN + 4];
 
-    const int ti = blockIdx.x % p.tiles_m, tj = blockIdx.x / p.tiles_m;
+    int ti, tj;
+    tile_of(blockIdx.x, gridDim.x, p.tiles_m,
+            p.tmode == T_ALL && (p.kmode == K_FULL || p.kmode == K_A_HERM_LOWER), ti, tj);
     // triangle modes skip tiles whose every element lies on the other side
     if ((p.tmode == T_UPPER_TILES || p.tmode == T_UPPER_STRICT) && ti * BM > tj * BN + BN - 1) return;
     if ((p.tmode == T_LOWER_TILES || p.tmode == T_LOWER_STRICT) && ti * BM + BM - 1 < tj * BN) return;
