@@ -160,6 +160,11 @@ class Solver:
             _check(L.gevd_set_option(h, OPT_KSTATS, 1), "gevd_set_option")
         self.set_precision(precision, refine)
 
+    def set_kstats(self, on: bool):
+        """Enable or disable the per-family kernel accounting (HIP events
+        around every launch)."""
+        _check(load().gevd_set_option(self._h, OPT_KSTATS, 1 if on else 0), "gevd_set_option")
+
     def set_precision(self, precision: str = "fp64", refine: int = 2):
         """'fp64', or 'fp32+refine': full -> band and stage-1 back-transform
         products on the FP32 matrix cores, then `refine` FP64 refinement
