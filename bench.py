@@ -44,10 +44,10 @@ def nominal_flops(n: int, k: int, cplx: bool) -> float:
     return 4.0 * f if cplx else f
 
 
-def measured_traffic(config: str, family: str):
+def measured_traffic(config: str, family: str, band: int):
     """HBM bytes per launch of a kernel family from the committed PMC
-    summary (profiles/), or None when there is none for this workload or the
-    kernel source changed since the counters were taken."""
+    summary (profiles/), or None when there is none for this workload and
+    band width, or the kernel source changed since the counters were taken."""
     import hashlib
 
     path = os.path.join(ROOT, "profiles", "%s_family_%s_traffic.json" % (family, config))
@@ -55,6 +55,8 @@ def measured_traffic(config: str, family: str):
         return None
     with open(path) as f:
         rec = json.load(f)
+    if rec.get("band") != band:
+        return None
     src = os.path.join(ROOT, rec["source"])
     if not os.path.exists(src):
         return None
@@ -263,7 +265,7 @@ def main():
     ach = g["flops"] / (g["ms"] / 1e3) / 1e12 if g["ms"] > 0 else 0.0
     out["roofline"] = {"kernel": dom, "bound": FAMILY_BOUND[dom], "achieved": round(ach, 3),
                        "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(ach / FP64_PEAK_TFLOPS, 4),
-                       "traffic": measured_traffic(args.config, dom), "launches_per_step": g["launches"] // kstat_steps,
+                       "traffic": measured_traffic(args.config, dom, solver.band_width(n, H0.dtype)), "launches_per_step": g["launches"] // kstat_steps,
                        "avg_launch_ms": round(g["ms"] / g["launches"], 4)}
     if not args.no_fp32:
         # the same workload in the reduced-precision form, compared with the

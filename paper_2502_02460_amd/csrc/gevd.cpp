@@ -109,8 +109,11 @@ void attach_aux(gevd_ctx* h, StageCtx& sc) {
     sc.join = h->aux_join;
 }
 
+// Default half-bandwidth: 64 for large orders (fewer, wider panels and
+// bulge-reflector groups; the four-wave bulge-chasing kernel keeps the
+// band -> tridiagonal stage in check), 32 below that.
 int pick_band(const gevd_ctx* h, int n) {
-    int b = h->band_opt > 0 ? h->band_opt : 32;
+    int b = h->band_opt > 0 ? h->band_opt : (n >= 4096 ? 64 : 32);
     if (n <= 2 * b) b = std::max(1, std::min(b, n / 2));
     return std::max(1, b);
 }

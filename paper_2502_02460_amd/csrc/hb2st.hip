@@ -243,6 +243,207 @@ __global__ __launch_bounds__(64) void hb2st_kernel(int n, int b, T* Bw, long ldw
 #undef DL_
 }
 
+// Four-wave variant for wider bands (b > 32), where the single wave's row
+// loops dominate a task: row i of the blocks is handled by lane i of every
+// wave, the four waves split the inner index of each block product into
+// quarters and add their partial sums in a fixed order (deterministic).
+constexpr int CW = 4;  // waves per workgroup
+constexpr int LB4 = 8;  // independent loads per lane per batch
+
+template <typename T>
+__global__ __launch_bounds__(64 * CW) void hb2st_kernel_wg(int n, int b, T* Bw, long ldw, T* V2, T* tau2, int nsw,
+                                                          int* progress, int* counter, int* hang) {
+    extern __shared__ char lds_raw[];
+    T* Eb = reinterpret_cast<T*>(lds_raw);
+    T* Db = Eb + (size_t)b * (b + 1);
+    const int ldl = b + 1;
+    __shared__ T v[MAXB], vp[MAXB], y[MAXB];
+    __shared__ T part[CW][MAXB];
+    __shared__ T sc[4];
+    __shared__ T ptau;
+    __shared__ int sw_s, stop;
+    const int tid = threadIdx.x, lane = tid % WAVE, wv = tid / WAVE;
+    constexpr int NT = 64 * CW;
+    const int q = (b + CW - 1) / CW;  // inner-index quarter
+#define EL_(i, j) Eb[(i) * ldl + (j)]
+#define DL_(i, j) Db[(i) * ldl + (j)]
+
+    for (;;) {
+        if (tid == 0) {
+            sw_s = atomicAdd(counter, 1);
+            stop = 0;
+        }
+        __syncthreads();
+        const int sw = sw_s;
+        if (sw >= nsw) return;
+        const int nt = ntasks(n, b, sw);
+        for (int t = 0; t < nt; ++t) {
+            if (sw > 0) {
+                if (tid == 0) {
+                    const int need = min(t + 2, ntasks(n, b, sw - 1));
+                    unsigned spins = 0;
+                    unsigned long long t_start = 0;
+                    // polling as in the single-wave kernel
+                    while (__hip_atomic_load(&progress[sw - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+                        if ((++spins & 63u) == 0) {
+                            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                            const unsigned long long now = wall_clock64();
+                            if (t_start == 0) t_start = now;
+                            if (now - t_start > WAIT_LIMIT_TICKS ||
+                                __hip_atomic_load(hang, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                                atomicOr(hang, 1);
+                                stop = 1;
+                                break;
+                            }
+                        }
+                        __builtin_amdgcn_s_sleep(1);
+                    }
+                }
+                __syncthreads();
+                if (stop) return;
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            }
+            const int r0 = sw + 1 + t * b;
+            const int L = min(b, n - r0);
+            const int pr0 = r0 - b;
+            {
+                const int ne = (t > 0) ? L * b : 0, nd = L * L;
+                for (int base = 0; base < ne + nd; base += NT * LB4) {
+                    T tmp[LB4];
+#pragma unroll
+                    for (int k = 0; k < LB4; ++k) {
+                        const int e = base + tid + NT * k;
+                        tmp[k] = zero_of<T>();
+                        if (e < ne) {
+                            const int i = e % L, j = e / L;
+                            tmp[k] = Bw[IDX(b + i - j, pr0 + j, ldw)];
+                        } else if (e < ne + nd) {
+                            const int f = e - ne, i = f % L, j = f / L;
+                            if (i >= j) tmp[k] = Bw[IDX(i - j, r0 + j, ldw)];
+                        }
+                    }
+#pragma unroll
+                    for (int k = 0; k < LB4; ++k) {
+                        const int e = base + tid + NT * k;
+                        if (e < ne) {
+                            const int i = e % L, j = e / L;
+                            EL_(i, j) = tmp[k];
+                        } else if (e < ne + nd) {
+                            const int f = e - ne, i = f % L, j = f / L;
+                            if (i >= j) {
+                                DL_(i, j) = tmp[k];
+                                DL_(j, i) = conjg(tmp[k]);
+                            }
+                        }
+                    }
+                }
+                if (t == 0 && tid < L) v[tid] = Bw[IDX(1 + tid, sw, ldw)];
+                __syncthreads();
+            }
+            const int j0 = wv * q, j1 = min(b, j0 + q);
+            if (t == 0) {
+                reflect1<T>(v, L, sc);
+                if (tid < L) Bw[IDX(1 + tid, sw, ldw)] = (tid == 0) ? sc[1] : zero_of<T>();
+            } else {
+                if (lane < L) {
+                    T acc = zero_of<T>();
+                    for (int j = j0; j < j1; ++j) acc += EL_(lane, j) * vp[j];
+                    part[wv][lane] = acc;
+                }
+                __syncthreads();
+                if (lane < L) {
+                    T acc = part[0][lane];
+#pragma unroll
+                    for (int w = 1; w < CW; ++w) acc += part[w][lane];
+                    const T pa = ptau * acc;
+                    for (int j = j0; j < j1; ++j) EL_(lane, j) -= pa * conjg(vp[j]);
+                    if (j0 == 0) v[lane] = EL_(lane, 0);
+                }
+                __syncthreads();
+                if (L >= 2) {
+                    reflect1<T>(v, L, sc);
+                    const int qi = (L + CW - 1) / CW, i0 = wv * qi, i1 = min(L, i0 + qi);
+                    if (lane < b) {
+                        T acc = zero_of<T>();
+                        for (int i = i0; i < i1; ++i) acc += conjg(v[i]) * EL_(i, lane);
+                        part[wv][lane] = acc;
+                    }
+                    __syncthreads();
+                    if (tid < b) {
+                        T acc = part[0][tid];
+#pragma unroll
+                        for (int w = 1; w < CW; ++w) acc += part[w][tid];
+                        y[tid] = acc;
+                    }
+                    __syncthreads();
+                    const T ctau = conjg(sc[0]);
+                    for (int e = tid; e < L * b; e += NT) {
+                        const int i = e % L, j = e / L;
+                        if (j == 0) Bw[IDX(b + i, pr0, ldw)] = (i == 0) ? sc[1] : zero_of<T>();
+                        else Bw[IDX(b + i - j, pr0 + j, ldw)] = EL_(i, j) - ctau * v[i] * y[j];
+                    }
+                } else {
+                    if (tid == 0) {
+                        v[0] = from_real<T>(1.0);
+                        sc[0] = zero_of<T>();
+                    }
+                    for (int e = tid; e < L * b; e += NT) {
+                        const int i = e % L, j = e / L;
+                        Bw[IDX(b + i - j, pr0 + j, ldw)] = EL_(i, j);
+                    }
+                    __syncthreads();
+                }
+            }
+            const T tau = sc[0];
+            if (!is_zero(tau)) {
+                const int qj = (L + CW - 1) / CW, c0 = wv * qj, c1 = min(L, c0 + qj);
+                if (lane < L) {
+                    T acc = zero_of<T>();
+                    for (int j = c0; j < c1; ++j) acc += DL_(lane, j) * v[j];
+                    part[wv][lane] = acc;
+                }
+                __syncthreads();
+                if (tid < WAVE) {
+                    T yl = zero_of<T>();
+                    if (lane < L) {
+                        T acc = part[0][lane];
+#pragma unroll
+                        for (int w = 1; w < CW; ++w) acc += part[w][lane];
+                        yl = tau * acc;
+                    }
+                    T yv = (lane < L) ? conjg(yl) * v[lane] : zero_of<T>();
+                    yv = wave_sum(yv);
+                    const T coef = from_real<T>(-0.5) * tau * yv;
+                    if (lane < L) y[lane] = yl + coef * v[lane];
+                }
+                __syncthreads();
+                for (int e = tid; e < L * L; e += NT) {
+                    const int i = e % L, j = e / L;
+                    if (i >= j) {
+                        T x = DL_(i, j) - v[i] * conjg(y[j]) - y[i] * conjg(v[j]);
+                        if (i == j) x = from_real<T>(realp(x));
+                        Bw[IDX(i - j, r0 + j, ldw)] = x;
+                    }
+                }
+            }
+            const size_t slot = (size_t)t * nsw + sw;
+            if (tid < b) V2[slot * b + tid] = (tid < L) ? v[tid] : zero_of<T>();
+            if (tid == 0) tau2[slot] = tau;
+            __syncthreads();
+            if (tid < MAXB) vp[tid] = (tid < L) ? v[tid] : zero_of<T>();
+            if (tid == 0) ptau = tau;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            __syncthreads();
+            if (tid == 0) {
+                __hip_atomic_store(&progress[sw], t + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // write the counter back (see above)
+            }
+        }
+    }
+#undef EL_
+#undef DL_
+}
+
 template <typename T>
 __global__ void extract_tridiag(int n, const T* Bw, long ldw, double* d, double* e) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -569,12 +770,18 @@ int hb2st(const StageCtx& c, int n, T* Bw, long ldw, ChaseRefl<T>& R, double* d,
         int* counter = sync_area + R.nsw + 1;
         const int grid = std::min(R.nsw, 1024);
         const size_t lds = (size_t)2 * b * (b + 1) * sizeof(T);
-        GEVD_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&hb2st_kernel<T>),
+        const bool wide = b > 32;  // four waves per sweep pay off only for wider bands
+        GEVD_HIP(hipFuncSetAttribute(wide ? reinterpret_cast<const void*>(&hb2st_kernel_wg<T>)
+                                          : reinterpret_cast<const void*>(&hb2st_kernel<T>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         // algorithmic work: about 6 n^2 b real flops (x4 complex)
         KProbe probe(st, GEVD_K_CHASE, (is_cplx<T>::value ? 24.0 : 6.0) * (double)n * n * b);
-        hipLaunchKernelGGL(hb2st_kernel<T>, dim3(grid), dim3(64), lds, st, n, b, Bw, ldw, R.V2, R.tau2, R.nsw, progress,
-                           counter, c.hang);
+        if (wide)
+            hipLaunchKernelGGL(hb2st_kernel_wg<T>, dim3(grid), dim3(64 * CW), lds, st, n, b, Bw, ldw, R.V2, R.tau2,
+                               R.nsw, progress, counter, c.hang);
+        else
+            hipLaunchKernelGGL(hb2st_kernel<T>, dim3(grid), dim3(64), lds, st, n, b, Bw, ldw, R.V2, R.tau2, R.nsw,
+                               progress, counter, c.hang);
         GEVD_LAUNCH_CHECK();
     }
     hipLaunchKernelGGL(extract_tridiag<T>, dim3((n + 255) / 256), dim3(256), 0, st, n, (const T*)Bw, ldw, d, e);

@@ -10,6 +10,7 @@ eigenvectors through residuals, orthogonality and phase-invariant overlaps.
 from __future__ import annotations
 
 import numpy as np
+import torch
 import pytest
 import scipy.linalg as sl
 
@@ -218,3 +219,31 @@ def test_solve_parity(solver, n, frac, smin, cplx):
     assert err < 1e-10
     assert eta < 1e-11
     assert orth < max(1e-11, 10 * orth_ref)
+
+
+# ------------------------------------------- wide bands (four-wave bulge chasing)
+@pytest.mark.parametrize("cplx", [False, True])
+@pytest.mark.parametrize("n,b", [(129, 40), (300, 64), (700, 64), (333, 48)])
+def test_wide_band_tridiagonal_and_solve(gpu_lib, n, b, cplx):
+    s = gpu_lib.Solver(band=b)
+    assert s.band_width(n, torch.complex128 if cplx else torch.float64) == b
+    p = synth.pencil(n, cplx, 1e-6, 1100 + n + b, 0.3)
+    A0 = oracle.reduce(p.H, oracle.cholesky(p.S))
+    d, e = s.tridiagonalize(dev(A0))
+    d, e = host(d), host(e)
+    w, _ = oracle.tql(d, e, vectors=False)
+    dr, er, _, _ = oracle.tridiag(A0)
+    w_tri, _ = oracle.tql(dr, er, vectors=False)
+    err_t = np.abs(w - w_tri).max() / np.abs(w_tri).max()
+    w_ref, C_ref, _ = oracle.gevd(p.H, p.S, p.k)
+    ws, C = s.solve(dev(p.H), dev(p.S), p.k)
+    ws, C = host(ws), host(C)
+    err = np.abs(ws - w_ref).max() / np.abs(w_ref).max()
+    eta = backward_errors(p.H, p.S, ws[: p.k], C).max()
+    orth, orth_ref = s_orthonormality(p.S, C), s_orthonormality(p.S, C_ref)
+    log(f"wide band n={n} b={b} cplx={cplx}: tridiag eig {err_t:.2e}; solve eig {err:.2e} eta {eta:.2e} "
+        f"orth {orth:.2e} (oracle {orth_ref:.2e})")
+    assert err_t < tol_eig(n)
+    assert err < 1e-10 and eta < 1e-11
+    assert orth < max(1e-11, 10 * orth_ref)
+    s.close()
