@@ -248,7 +248,7 @@ __global__ __launch_bounds__(64) void hb2st_kernel(int n, int b, T* Bw, long ldw
 // wave, the four waves split the inner index of each block product into
 // quarters and add their partial sums in a fixed order (deterministic).
 constexpr int CW = 4;  // waves per workgroup
-constexpr int LB4 = 8;  // independent loads per lane per batch
+constexpr int LB4 = 32;  // independent loads per lane per batch (b = 64: one batch)
 
 template <typename T>
 __global__ __launch_bounds__(64 * CW) void hb2st_kernel_wg(int n, int b, T* Bw, long ldw, T* V2, T* tau2, int nsw,
