@@ -230,13 +230,10 @@ __global__ __launch_bounds__(64) void hb2st_kernel(int n, int b, T* Bw, long ldw
             if (lane == 0) ptau = tau;
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // this wave's band stores, device-wide
             __syncthreads();
-            if (lane == 0) {
-                __hip_atomic_store(&progress[sw], t + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-                // A release orders the earlier stores before the counter; it
-                // does not push the counter itself out of this XCD's L2, so
-                // a waiter on another XCD could see it late.  Write it back.
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-            }
+            // The counter is stored at system scope: written through, not
+            // left in this XCD's L2 where a waiter on another XCD would see
+            // it late (the fence above already ordered the band stores).
+            if (lane == 0) __hip_atomic_store(&progress[sw], t + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
         }
     }
 #undef EL_
@@ -434,10 +431,7 @@ __global__ __launch_bounds__(64 * CW) void hb2st_kernel_wg(int n, int b, T* Bw, 
             if (tid == 0) ptau = tau;
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             __syncthreads();
-            if (tid == 0) {
-                __hip_atomic_store(&progress[sw], t + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // write the counter back (see above)
-            }
+            if (tid == 0) __hip_atomic_store(&progress[sw], t + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
         }
     }
 #undef EL_
