@@ -28,7 +28,14 @@ struct PanelScratch {
     T scale;
     double beta;
     unsigned counter;
+    unsigned bar;        // grid barrier of the persistent panel kernel (monotonic)
+    T prow[2][MAXB];     // pivot row of the current column (by column parity)
 };
+
+// Largest grid of the persistent panel kernel (all its workgroups must be
+// resident together; larger panels use one launch per column).
+constexpr int PANEL_MAX_WG = 512;
+constexpr unsigned long long PANEL_WAIT_TICKS = 120ull * 100000000ull;  // 120 s at 100 MHz
 
 template <typename T>
 __device__ inline void make_reflector(T alpha, double xn2, T* tau, T* scale, double* beta) {
@@ -164,6 +171,150 @@ __global__ __launch_bounds__(PT) void panel_step(T* P, long lda, int m, int b, i
     if (tid == 0) P[IDX(s, s, lda)] = from_real<T>(bt);
 }
 
+// The whole panel in one launch: every workgroup owns PT rows for all
+// columns and keeps them in registers, so the panel is read and written
+// once.  Per column: apply the previous reflector to the own rows, write
+// the column's partial sums (and the pivot row, by its owner), one grid
+// barrier, then every workgroup adds all partials in workgroup order (the
+// same values everywhere, deterministic) and forms the reflector itself.
+// All workgroups are resident together (the grid is at most PANEL_MAX_WG
+// small workgroups), so every barrier is reached; a time bound turns a
+// broken invariant into an error flag.  bar_base: barrier count before this
+// panel (the counter is zeroed once per reduction).
+template <typename T>
+__global__ __launch_bounds__(PT) void panel_all(T* P, long lda, int m, int b, int nref, T* Vp, PanelScratch<T>* ps,
+                                                T* partial, unsigned bar_base, int* hang) {
+    __shared__ T red[PT / WAVE][MAXB + 1];
+    __shared__ T wsh[MAXB];
+    __shared__ T gath[GCH][MAXB + 1];
+    __shared__ T acc_lds[MAXB + 1];
+    __shared__ T fin[2];  // tau, scale of the current reflector
+    __shared__ double bt;
+    __shared__ int stop;
+    const int tid = threadIdx.x, w = tid / WAVE, l = tid % WAVE;
+    const int G = gridDim.x;
+    const int r = blockIdx.x * PT + tid;
+    const bool inr = r < m;
+    T row[MAXB];
+#pragma unroll
+    for (int j = 0; j < MAXB; ++j) row[j] = (inr && j < b) ? P[IDX(r, j, lda)] : zero_of<T>();
+    if (tid == 0) stop = 0;
+    for (int s = 0; s <= nref; ++s) {
+        if (s > 0) {
+            const int sp = s - 1;
+            T v = zero_of<T>();
+#pragma unroll
+            for (int j = 0; j < MAXB; ++j)
+                if (j == sp) v = (r == sp) ? from_real<T>(1.0) : (r > sp ? row[j] * fin[1] : zero_of<T>());
+            if (inr) {
+                Vp[IDX(r, sp, m)] = v;
+                const T ctv = conjg(fin[0]) * v;
+#pragma unroll
+                for (int j = 0; j < MAXB; ++j)
+                    if (j >= s && j < b) row[j] -= ctv * wsh[j];
+            }
+        }
+        if (s >= nref) break;
+        const int par = s & 1;
+        if (r == s) {
+#pragma unroll
+            for (int j = 0; j < MAXB; ++j)
+                if (j >= s && j < b) ps->prow[par][j] = row[j];
+        }
+        const bool below = r > s && inr;
+        T x = zero_of<T>();
+#pragma unroll
+        for (int j = 0; j < MAXB; ++j)
+            if (j == s && below) x = row[j];
+        const double nx = wave_sum(abs2(x));
+        if (l == 0) red[w][MAXB] = from_real<T>(nx);
+        const T cx = conjg(x);
+#pragma unroll
+        for (int j = 0; j < MAXB; ++j)
+            if (j > s && j < b) {
+                const T y = wave_sum(cx * row[j]);
+                if (l == 0) red[w][j] = y;
+            }
+        __syncthreads();
+        T* part = partial + ((size_t)par * G + blockIdx.x) * (MAXB + 1);
+        if ((tid > s && tid < b) || tid == MAXB) {
+            T acc = red[0][tid];
+            for (int q = 1; q < PT / WAVE; ++q) acc += red[q][tid];
+            part[tid] = acc;
+        }
+        // grid barrier for column s
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __syncthreads();
+        if (tid == 0) {
+            const unsigned target = bar_base + (unsigned)(s + 1) * (unsigned)G;
+            __hip_atomic_fetch_add(&ps->bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            unsigned spins = 0;
+            unsigned long long t0 = 0;
+            while (__hip_atomic_load(&ps->bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+                if ((++spins & 63u) == 0) {
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                    const unsigned long long now = wall_clock64();
+                    if (t0 == 0) t0 = now;
+                    if (now - t0 > PANEL_WAIT_TICKS ||
+                        __hip_atomic_load(hang, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                        atomicOr(hang, 1);
+                        stop = 1;
+                        break;
+                    }
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+        __syncthreads();
+        if (stop) return;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        // all partials of column s, added in workgroup order
+        if (tid <= MAXB) acc_lds[tid] = zero_of<T>();
+        for (int g0 = 0; g0 < G; g0 += GCH) {
+            const int rows = min(GCH, G - g0);
+            __syncthreads();
+            for (int e = tid; e < rows * (MAXB + 1); e += PT) {
+                const int g = e / (MAXB + 1), c = e % (MAXB + 1);
+                gath[g][c] = ((c > s && c < b) || c == MAXB)
+                                 ? partial[((size_t)par * G + g0 + g) * (MAXB + 1) + c] : zero_of<T>();
+            }
+            __syncthreads();
+            if (tid <= MAXB) {
+                T acc = acc_lds[tid];
+                for (int g = 0; g < rows; ++g) acc += gath[g][tid];
+                acc_lds[tid] = acc;
+            }
+        }
+        __syncthreads();
+        if (tid == 0) {
+            T tau, scale;
+            double beta;
+            make_reflector<T>(ps->prow[par][s], realp(acc_lds[MAXB]), &tau, &scale, &beta);
+            fin[0] = tau;
+            fin[1] = scale;
+            bt = beta;
+            if (blockIdx.x == 0) {
+                ps->tau[s] = tau;
+                ps->scale = scale;
+                ps->beta = beta;
+            }
+        }
+        __syncthreads();
+        if (tid > s && tid < b) wsh[tid] = conjg(fin[1]) * acc_lds[tid] + ps->prow[par][tid];
+        if (r == s) {
+#pragma unroll
+            for (int j = 0; j < MAXB; ++j)
+                if (j == s) row[j] = from_real<T>(bt);
+        }
+        __syncthreads();
+    }
+    if (inr) {
+#pragma unroll
+        for (int j = 0; j < MAXB; ++j)
+            if (j < b) P[IDX(r, j, lda)] = row[j];
+    }
+}
+
 // T (b x b upper) of Q = H_0 ... H_{b-1} = I - V T V^H from the Gram matrix
 // G = V^H V: T[s, s] = tau_s, T[0:s, s] = -tau_s T[0:s, 0:s] G[0:s, s].
 template <typename T>
@@ -245,7 +396,7 @@ size_t carve_ws(char* base, int n, int b, He2hbWs<T>* w) {
     t.M2 = c.take<T>((size_t)b * b);
     t.skS = c.take<T>((size_t)SK * b * b);
     const size_t nwg = (size_t)(n + PT - 1) / PT + 1;
-    t.partialT = c.take<T>(nwg * (MAXB + 1));
+    t.partialT = c.take<T>(2 * nwg * (MAXB + 1));
     t.partialD = c.take<double>(nwg);
     t.ps = c.take<PanelScratch<T>>(1);
     if (w) *w = t;
@@ -273,6 +424,7 @@ int he2hb(const StageCtx& c, int n, T* A, long lda, BandRefl<T>& R, T* Bd, long 
     int rc;
     const bool look = c.aux != nullptr && c.fork != nullptr && c.join != nullptr;
     bool pending = false;
+    unsigned bar_base = 0;  // grid-barrier count of the persistent panel kernel
     // the panel scratch counter must start at zero
     if ((rc = set_zero<T>(st, (int)((sizeof(PanelScratch<T>) + sizeof(T) - 1) / sizeof(T)), 1, (T*)w.ps, 1)))
         return rc;
@@ -283,14 +435,28 @@ int he2hb(const StageCtx& c, int n, T* A, long lda, BandRefl<T>& R, T* Bd, long 
         T* P = A + IDX(c0 + b, c0, lda);
         T* Vp = R.V + R.voff(p);
         T* Tp = R.Tf + (size_t)p * b * b;
-        if ((rc = set_zero<T>(st, m, b, Vp, m))) return rc;
-        for (int s = 0; s <= nref; ++s) {
-            const int r0 = s > 0 ? s - 1 : 0;
-            const unsigned g = (unsigned)((m - r0 + PT - 1) / PT);
-            KProbe probe(st, GEVD_K_PANEL,
-                         (is_cplx<T>::value ? 16.0 : 4.0) * (double)(m - r0) * std::max(0, b - s));
-            hipLaunchKernelGGL(panel_step<T>, dim3(g), dim3(PT), 0, st, P, lda, m, b, s, nref, Vp, w.ps, w.partialT);
+        const int gall = (m + PT - 1) / PT;
+        if (gall <= PANEL_MAX_WG && c.hang) {
+            // one persistent launch for the panel (writes columns 0 .. nref-1 of Vp)
+            if (nref < b && (rc = set_zero<T>(st, m, b, Vp, m))) return rc;
+            double fl = 0.0;
+            for (int s = 0; s <= nref; ++s) fl += (double)(m - (s > 0 ? s - 1 : 0)) * std::max(0, b - s);
+            KProbe probe(st, GEVD_K_PANEL, (is_cplx<T>::value ? 16.0 : 4.0) * fl);
+            hipLaunchKernelGGL(panel_all<T>, dim3(gall), dim3(PT), 0, st, P, lda, m, b, nref, Vp, w.ps, w.partialT,
+                               bar_base, c.hang);
             GEVD_LAUNCH_CHECK();
+            bar_base += (unsigned)nref * (unsigned)gall;
+        } else {
+            if ((rc = set_zero<T>(st, m, b, Vp, m))) return rc;
+            for (int s = 0; s <= nref; ++s) {
+                const int r0 = s > 0 ? s - 1 : 0;
+                const unsigned g = (unsigned)((m - r0 + PT - 1) / PT);
+                KProbe probe(st, GEVD_K_PANEL,
+                             (is_cplx<T>::value ? 16.0 : 4.0) * (double)(m - r0) * std::max(0, b - s));
+                hipLaunchKernelGGL(panel_step<T>, dim3(g), dim3(PT), 0, st, P, lda, m, b, s, nref, Vp, w.ps,
+                                   w.partialT);
+                GEVD_LAUNCH_CHECK();
+            }
         }
         // T factor from G = V^H V
         if ((rc = gemm<T>(st, OP_C, OP_N, b, b, m, one, Vp, m, Vp, m, zero, w.G, b, K_FULL, T_ALL, Batch(), SK,
