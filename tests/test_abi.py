@@ -67,3 +67,30 @@ def test_strerror_and_workspace(lib):
     assert 0 < small < big
     # complex needs more than real at the same size
     assert lib.gevd_workspace_bytes(1, 512, 128) > lib.gevd_workspace_bytes(0, 512, 128)
+
+
+def test_batched_entry_points_validate_on_host(lib):
+    P, I = ctypes.c_void_p, ctypes.c_int
+    lib.gevd_solve_batched.argtypes = [P, I, P, P]
+    assert lib.gevd_solve_batched(None, 1, None, None) == -1
+    lib.gevd_batch_create.argtypes = [P, I, P, P]
+    assert lib.gevd_batch_create(None, 1, None, None) == -1
+    lib.gevd_batch_run.argtypes = [P, P]
+    assert lib.gevd_batch_run(None, None) == -1
+    lib.gevd_batch_destroy.argtypes = [P]
+    assert lib.gevd_batch_destroy(None) == -1
+    lib.gevd_set_batch_shape.argtypes = [P, I, I, I, I]
+    assert lib.gevd_set_batch_shape(None, 0, 64, 256, 1) == -1
+    lib.gevd_tune_batched.argtypes = [P, I, I, I, P, P]
+    assert lib.gevd_tune_batched(None, 0, 64, 8, None, None) == -1
+    lib.gevd_set_overlap.argtypes = [P, I, I, P, I]
+    assert lib.gevd_set_overlap(None, 0, 4, None, 4) == -1
+
+
+def test_bench_refuses_several_gpus():
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
