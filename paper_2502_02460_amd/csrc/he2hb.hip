@@ -7,9 +7,11 @@
 // H_s = I - tau_s v_s v_s^H (beta real), then the trailing m x m block is
 // updated two-sidedly with the compact WY form Q = I - V T V^H:
 //   X = A22 V T,  W = X - 1/2 V (T^H V^H X),  A22 <- A22 - W V^H - V W^H,
-// all as MFMA products.  The panel QR is latency-bound: each column costs one
-// row-parallel launch whose reductions finish in the last workgroup to
-// arrive (fixed summation order, so results are deterministic).
+// all as MFMA products.  The panel QR is latency-bound: one persistent
+// launch per panel with a grid barrier per column (very tall panels: one
+// row-parallel launch per column whose reductions finish in the last
+// workgroup to arrive); sums run in a fixed order, so results are
+// deterministic.
 #include <algorithm>
 
 #include "stages.hpp"
@@ -32,9 +34,11 @@ struct PanelScratch {
     T prow[2][MAXB];     // pivot row of the current column (by column parity)
 };
 
-// Largest grid of the persistent panel kernel (all its workgroups must be
-// resident together; larger panels use one launch per column).
-constexpr int PANEL_MAX_WG = 512;
+// Largest grid of the persistent panel kernel: all its workgroups (one CU
+// each) must be resident together, also beside the persistent panels of a
+// few concurrent solves on the same device; larger panels use one launch
+// per column.
+constexpr int PANEL_MAX_WG = 64;
 constexpr unsigned long long PANEL_WAIT_TICKS = 120ull * 100000000ull;  // 120 s at 100 MHz
 
 template <typename T>
@@ -171,147 +175,172 @@ __global__ __launch_bounds__(PT) void panel_step(T* P, long lda, int m, int b, i
     if (tid == 0) P[IDX(s, s, lda)] = from_real<T>(bt);
 }
 
-// The whole panel in one launch: every workgroup owns PT rows for all
-// columns and keeps them in registers, so the panel is read and written
-// once.  Per column: apply the previous reflector to the own rows, write
-// the column's partial sums (and the pivot row, by its owner), one grid
-// barrier, then every workgroup adds all partials in workgroup order (the
-// same values everywhere, deterministic) and forms the reflector itself.
-// All workgroups are resident together (the grid is at most PANEL_MAX_WG
-// small workgroups), so every barrier is reached; a time bound turns a
-// broken invariant into an error flag.  bar_base: barrier count before this
-// panel (the counter is zeroed once per reduction).
+// Value of v in lane `lane` of the wavefront (lane uniform), as a scalar
+// broadcast: two 32-bit lane reads per double.
+__device__ inline double lane_bcast(double v, int lane) {
+    const long long u = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)u, lane);
+    const int hi = __builtin_amdgcn_readlane((int)(u >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ inline zdouble lane_bcast(zdouble v, int lane) { return {lane_bcast(v.x, lane), lane_bcast(v.y, lane)}; }
+
+// The whole panel in one launch, column-parallel: lane j of every wave owns
+// column j of RPW consecutive panel rows and keeps them in registers, so the
+// panel is read and written once and the row sums of a column step are
+// per-lane sums (no cross-lane reduction).  Per column s:
+//  1. apply reflector s-1: a[i] -= x_i * (scale conj(tau) w_j), with x the
+//     reflector's column broadcast from its lane (rows <= s-1 are zero there,
+//     see 2);
+//  2. the wave holding row s takes the pivot row out of its registers (kept
+//     in pv and published for the other workgroups) and zeroes it, so every
+//     lane's rows <= s are zero from now on;
+//  3. y_j = sum_i conj(x_i) a_j[i] over the wave's rows (x = column s, so
+//     y_s = ||x||^2), added over the waves in fixed order and written as the
+//     workgroup's partial;
+//  4. one grid barrier; every workgroup adds all partials in workgroup order
+//     (the same values everywhere, deterministic) and forms reflector s and
+//     w_j = v^H P[:, j] = conj(scale) y_j + P[s, j] itself;
+//  5. the wave holding row s stores the finished row s of the panel (beta on
+//     the diagonal, P[s, j] - conj(tau) w_j right of it, the x entries of the
+//     finished columns left of it) and of V.
+// The rows at and below nref are stored once at the end.  All workgroups
+// are resident together (one per CU at most PANEL_MAX_WG), so every barrier
+// is reached; a time bound turns a broken invariant into an error flag.
+// bar_base: barrier count before this panel (the counter is zeroed once per
+// reduction).
+constexpr int RPW = 32;                  // panel rows per wave
+constexpr int PNW = PT / RPW;            // waves per workgroup (PT rows)
+constexpr int PCT = PNW * WAVE;          // threads per workgroup
 template <typename T>
-__global__ __launch_bounds__(PT) void panel_all(T* P, long lda, int m, int b, int nref, T* Vp, PanelScratch<T>* ps,
-                                                T* partial, unsigned bar_base, int* hang) {
-    __shared__ T red[PT / WAVE][MAXB + 1];
-    __shared__ T wsh[MAXB];
-    __shared__ T gath[GCH][MAXB + 1];
-    __shared__ T acc_lds[MAXB + 1];
-    __shared__ T fin[2];  // tau, scale of the current reflector
-    __shared__ double bt;
+__global__ __launch_bounds__(PCT) void panel_cols(T* P, long lda, int m, int b, int nref, T* Vp,
+                                                  PanelScratch<T>* ps, T* partial, unsigned bar_base, int* hang) {
+    __shared__ T ysh[PNW][WAVE];
+    __shared__ T ysum[PNW][WAVE];
     __shared__ int stop;
-    const int tid = threadIdx.x, w = tid / WAVE, l = tid % WAVE;
+    const int tid = threadIdx.x, g = tid / WAVE, j = tid % WAVE;
     const int G = gridDim.x;
-    const int r = blockIdx.x * PT + tid;
-    const bool inr = r < m;
-    T row[MAXB];
+    const int rb = blockIdx.x * PT + g * RPW;  // first panel row of this wave
+    const bool col = j < b;
+    T a[RPW];
 #pragma unroll
-    for (int j = 0; j < MAXB; ++j) row[j] = (inr && j < b) ? P[IDX(r, j, lda)] : zero_of<T>();
+    for (int i = 0; i < RPW; ++i) a[i] = (col && rb + i < m) ? P[IDX(rb + i, j, lda)] : zero_of<T>();
     if (tid == 0) stop = 0;
+    T tau = zero_of<T>(), scale = zero_of<T>(), wj = zero_of<T>(), myscale = zero_of<T>();
     for (int s = 0; s <= nref; ++s) {
         if (s > 0) {
             const int sp = s - 1;
-            T v = zero_of<T>();
+            const T ck = scale * (conjg(tau) * wj);  // zero outside columns s .. b-1
 #pragma unroll
-            for (int j = 0; j < MAXB; ++j)
-                if (j == sp) v = (r == sp) ? from_real<T>(1.0) : (r > sp ? row[j] * fin[1] : zero_of<T>());
-            if (inr) {
-                Vp[IDX(r, sp, m)] = v;
-                const T ctv = conjg(fin[0]) * v;
-#pragma unroll
-                for (int j = 0; j < MAXB; ++j)
-                    if (j >= s && j < b) row[j] -= ctv * wsh[j];
-            }
+            for (int i = 0; i < RPW; ++i) a[i] -= lane_bcast(a[i], sp) * ck;
         }
         if (s >= nref) break;
         const int par = s & 1;
-        if (r == s) {
+        const bool top = rb <= s && s < rb + RPW;  // this wave holds pivot row s
+        T pv = zero_of<T>();
+        if (top) {
 #pragma unroll
-            for (int j = 0; j < MAXB; ++j)
-                if (j >= s && j < b) ps->prow[par][j] = row[j];
-        }
-        const bool below = r > s && inr;
-        T x = zero_of<T>();
-#pragma unroll
-        for (int j = 0; j < MAXB; ++j)
-            if (j == s && below) x = row[j];
-        const double nx = wave_sum(abs2(x));
-        if (l == 0) red[w][MAXB] = from_real<T>(nx);
-        const T cx = conjg(x);
-#pragma unroll
-        for (int j = 0; j < MAXB; ++j)
-            if (j > s && j < b) {
-                const T y = wave_sum(cx * row[j]);
-                if (l == 0) red[w][j] = y;
-            }
-        __syncthreads();
-        T* part = partial + ((size_t)par * G + blockIdx.x) * (MAXB + 1);
-        if ((tid > s && tid < b) || tid == MAXB) {
-            T acc = red[0][tid];
-            for (int q = 1; q < PT / WAVE; ++q) acc += red[q][tid];
-            part[tid] = acc;
-        }
-        // grid barrier for column s
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        __syncthreads();
-        if (tid == 0) {
-            const unsigned target = bar_base + (unsigned)(s + 1) * (unsigned)G;
-            __hip_atomic_fetch_add(&ps->bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            unsigned spins = 0;
-            unsigned long long t0 = 0;
-            while (__hip_atomic_load(&ps->bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-                if ((++spins & 63u) == 0) {
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-                    const unsigned long long now = wall_clock64();
-                    if (t0 == 0) t0 = now;
-                    if (now - t0 > PANEL_WAIT_TICKS ||
-                        __hip_atomic_load(hang, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
-                        atomicOr(hang, 1);
-                        stop = 1;
-                        break;
-                    }
+            for (int i = 0; i < RPW; ++i)
+                if (rb + i == s) {
+                    pv = a[i];
+                    a[i] = zero_of<T>();
                 }
-                __builtin_amdgcn_s_sleep(1);
+            ps->prow[par][j] = pv;
+        }
+        // four interleaved partial sums, added in a fixed order
+        T y0 = zero_of<T>(), y1 = zero_of<T>(), y2 = zero_of<T>(), y3 = zero_of<T>();
+#pragma unroll
+        for (int i = 0; i < RPW; i += 4) {
+            y0 += conjg(lane_bcast(a[i], s)) * a[i];
+            y1 += conjg(lane_bcast(a[i + 1], s)) * a[i + 1];
+            y2 += conjg(lane_bcast(a[i + 2], s)) * a[i + 2];
+            y3 += conjg(lane_bcast(a[i + 3], s)) * a[i + 3];
+        }
+        ysh[g][j] = (y0 + y1) + (y2 + y3);
+        __syncthreads();
+        if (g == 0) {
+            T t = ysh[0][j];
+#pragma unroll
+            for (int q = 1; q < PNW; ++q) t += ysh[q][j];
+            partial[((size_t)par * G + blockIdx.x) * WAVE + j] = t;
+            // grid barrier for column s (the pivot row and the partials were
+            // stored by this wave)
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            if (j == 0) {
+                const unsigned target = bar_base + (unsigned)(s + 1) * (unsigned)G;
+                __hip_atomic_fetch_add(&ps->bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                unsigned spins = 0;
+                unsigned long long t0 = 0;
+                while (__hip_atomic_load(&ps->bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+                    if ((++spins & 63u) == 0) {
+                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                        const unsigned long long now = wall_clock64();
+                        if (t0 == 0) t0 = now;
+                        if (now - t0 > PANEL_WAIT_TICKS ||
+                            __hip_atomic_load(hang, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                            atomicOr(hang, 1);
+                            stop = 1;
+                            break;
+                        }
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                }
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             }
         }
         __syncthreads();
         if (stop) return;
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        // all partials of column s, added in workgroup order
-        if (tid <= MAXB) acc_lds[tid] = zero_of<T>();
-        for (int g0 = 0; g0 < G; g0 += GCH) {
-            const int rows = min(GCH, G - g0);
-            __syncthreads();
-            for (int e = tid; e < rows * (MAXB + 1); e += PT) {
-                const int g = e / (MAXB + 1), c = e % (MAXB + 1);
-                gath[g][c] = ((c > s && c < b) || c == MAXB)
-                                 ? partial[((size_t)par * G + g0 + g) * (MAXB + 1) + c] : zero_of<T>();
-            }
-            __syncthreads();
-            if (tid <= MAXB) {
-                T acc = acc_lds[tid];
-                for (int g = 0; g < rows; ++g) acc += gath[g][tid];
-                acc_lds[tid] = acc;
-            }
-        }
-        __syncthreads();
-        if (tid == 0) {
-            T tau, scale;
-            double beta;
-            make_reflector<T>(ps->prow[par][s], realp(acc_lds[MAXB]), &tau, &scale, &beta);
-            fin[0] = tau;
-            fin[1] = scale;
-            bt = beta;
-            if (blockIdx.x == 0) {
-                ps->tau[s] = tau;
-                ps->scale = scale;
-                ps->beta = beta;
-            }
-        }
-        __syncthreads();
-        if (tid > s && tid < b) wsh[tid] = conjg(fin[1]) * acc_lds[tid] + ps->prow[par][tid];
-        if (r == s) {
+        // all partials of column s: wave g adds workgroups g, g + PNW, ...
+        // (independent loads, four at a time), then the waves' sums in order
+        const T prj = ps->prow[par][j];
+        T acc = zero_of<T>();
+        for (int q0 = g; q0 < G; q0 += PNW * 4) {
+            T v[4];
 #pragma unroll
-            for (int j = 0; j < MAXB; ++j)
-                if (j == s) row[j] = from_real<T>(bt);
+            for (int u = 0; u < 4; ++u) {
+                const int q = q0 + u * PNW;
+                v[u] = q < G ? partial[((size_t)par * G + q) * WAVE + j] : zero_of<T>();
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) acc += v[u];
         }
+        ysum[g][j] = acc;
         __syncthreads();
+        T tot = ysum[0][j];
+#pragma unroll
+        for (int q = 1; q < PNW; ++q) tot += ysum[q][j];
+        double beta;
+        make_reflector<T>(lane_bcast(prj, s), realp(lane_bcast(tot, s)), &tau, &scale, &beta);
+        wj = (j > s && col) ? conjg(scale) * tot + prj : zero_of<T>();
+        if (j == s) myscale = scale;
+        if (top && col) {  // row s of the panel and of V is final
+            T pr = pv, vr = zero_of<T>();
+            if (j < s) {
+                vr = pv * myscale;
+            } else if (j == s) {
+                pr = from_real<T>(beta);
+                vr = from_real<T>(1.0);
+            } else {
+                pr = pv - conjg(tau) * wj;
+            }
+            P[IDX(s, j, lda)] = pr;
+            Vp[IDX(s, j, m)] = vr;
+        }
+        if (blockIdx.x == 0 && tid == 0) {
+            ps->tau[s] = tau;
+            ps->scale = scale;
+            ps->beta = beta;
+        }
     }
-    if (inr) {
+    if (col) {
 #pragma unroll
-        for (int j = 0; j < MAXB; ++j)
-            if (j < b) P[IDX(r, j, lda)] = row[j];
+        for (int i = 0; i < RPW; ++i) {
+            const int r = rb + i;
+            if (r < m && r >= nref) {
+                P[IDX(r, j, lda)] = a[i];
+                Vp[IDX(r, j, m)] = j < nref ? a[i] * myscale : zero_of<T>();
+            }
+        }
     }
 }
 
@@ -437,13 +466,12 @@ int he2hb(const StageCtx& c, int n, T* A, long lda, BandRefl<T>& R, T* Bd, long 
         T* Tp = R.Tf + (size_t)p * b * b;
         const int gall = (m + PT - 1) / PT;
         if (gall <= PANEL_MAX_WG && c.hang) {
-            // one persistent launch for the panel (writes columns 0 .. nref-1 of Vp)
-            if (nref < b && (rc = set_zero<T>(st, m, b, Vp, m))) return rc;
+            // one persistent launch for the panel (writes all m x b entries of Vp)
             double fl = 0.0;
             for (int s = 0; s <= nref; ++s) fl += (double)(m - (s > 0 ? s - 1 : 0)) * std::max(0, b - s);
             KProbe probe(st, GEVD_K_PANEL, (is_cplx<T>::value ? 16.0 : 4.0) * fl);
-            hipLaunchKernelGGL(panel_all<T>, dim3(gall), dim3(PT), 0, st, P, lda, m, b, nref, Vp, w.ps, w.partialT,
-                               bar_base, c.hang);
+            hipLaunchKernelGGL(panel_cols<T>, dim3(gall), dim3(PCT), 0, st, P, lda, m, b, nref, Vp, w.ps,
+                               w.partialT, bar_base, c.hang);
             GEVD_LAUNCH_CHECK();
             bar_base += (unsigned)nref * (unsigned)gall;
         } else {
