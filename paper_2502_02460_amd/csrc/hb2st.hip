@@ -457,9 +457,14 @@ __global__ void extract_tridiag(int n, const T* Bw, long ldw, double* d, double*
 // is applied to the window of Z rows as three small products on the MFMA
 // units: W = V^H Z, W <- T W, Z <- Z - V W.  The T factors of all groups are
 // formed beforehand, in parallel (forward accumulation from the Gram matrix
-// V^H V).  A workgroup owns 16 columns of Z and keeps the group's rows in an
-// LDS ring of 128 rows (a group spans at most 127 rows; consecutive groups
-// slide by b).
+// V^H V).  A workgroup (eight waves) owns 16 columns of Z and keeps the
+// group's rows in an LDS ring of 128 rows (a group spans at most 127 rows;
+// consecutive groups slide by b).  V is held dense in LDS (zeros outside the
+// staircase, rows padded against bank conflicts), so every product is a
+// fixed-length chain of MFMAs whose operands are loaded into registers
+// first: W's 16-row blocks with their inner range split over the waves
+// (partials added in a fixed order), T W in two halves of its inner range,
+// and one 16-row block of the window per wave for Z - V W.
 // ---------------------------------------------------------------------------
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
@@ -522,25 +527,39 @@ __device__ inline void mma4(dbl4& cr, dbl4& ci, double ar, double ai, double br,
 }
 
 template <typename T, int NBS>
-__global__ __launch_bounds__(256) void back_chase_kernel(int n, int b, int nsw, int nblk, const T* V2, const T* Tg,
-                                                         int nev, T* Z, long ldz) {
+__global__ __launch_bounds__(512) void back_chase_kernel(int n, int b, int nsw, int nblk, const T* V2, const T* Tg,
+                                                   int nev, T* Z, long ldz) {
     constexpr int CX = is_cplx<T>::value ? 1 : 0;
     constexpr int NC = CX + 1;
-    constexpr int CT = 16, RING = 2 * MAXB;
-    constexpr int NB1 = NBS / 16, P = 4 / NB1;
-    __shared__ double vc[NC][NBS][MAXB];   // reflector j, entry q
-    __shared__ double tm[NC][NBS][NBS];    // T row-major
-    __shared__ double zr[NC][RING][CT];    // Z rows, ring-indexed by absolute row
-    __shared__ double wp[NC][P][NBS][CT];  // partial V^H Z
-    __shared__ double w1[NC][NBS][CT];     // V^H Z, then T V^H Z
+    constexpr int NT = 512, NWV = NT / WAVE;
+    constexpr int CT = 16, CTP = CT + 1, RING = 2 * MAXB;
+    constexpr int NB1 = NBS / 16;                 // 16-row blocks of W = V^H Z
+    constexpr int PA = NWV / NB1;                 // parts of W's inner dimension
+    constexpr int KA = ((15 + MAXB + 3) / 4 + PA - 1) / PA;  // k-steps per part
+    constexpr int VR = NBS + MAXB + 4;            // dense V row (r index), = 4 mod 32
+    constexpr int TR = NBS + 4;
+    constexpr int KS = NBS / 4;                   // k-steps over the group's reflectors
+    constexpr int KP = KS / 2;                    // k-steps per part of T W
+    constexpr int NRB = (NBS + MAXB - 1 + 15) / 16;
+    static_assert(NRB <= NWV && 2 * NB1 <= NWV, "wave split");
+    static_assert(VR % 32 == 4 && TR % 32 == 4, "bank padding");
+    static_assert(16 * (NB1 - 1) + 4 * PA * KA <= VR, "dense V rows");
+    __shared__ double vd[NC][NBS][VR];
+    __shared__ double tm[NC][NBS][TR];
+    __shared__ double zr[NC][RING][CTP];
+    __shared__ double wp[NC][PA][NBS][CTP];
+    __shared__ double w1[NC][2][NBS][CTP];
     const int tid = threadIdx.x, lane = tid % WAVE, wv = tid / WAVE;
     const int c0 = blockIdx.x * CT;
     const int ncol = min(CT, nev - c0);
     const int li = lane % 16, lk = lane / 16;
+    for (int e = tid; e < NC * NBS * VR; e += NT) (&vd[0][0][0])[e] = 0.0;
+    for (int e = tid; e < NC * RING * CTP; e += NT) (&zr[0][0][0])[e] = 0.0;
+    for (int e = tid; e < NC * 2 * NBS * CTP; e += NT) (&w1[0][0][0][0])[e] = 0.0;
 
     auto load_rows = [&](int ra, int rb) {
         const int nr = rb - ra;
-        for (int e = tid; e < nr * CT; e += 256) {
+        for (int e = tid; e < nr * CT; e += NT) {
             const int r = ra + e % nr, c = e / nr;
             const T v = (c < ncol) ? Z[IDX(r, c0 + c, ldz)] : zero_of<T>();
             zr[0][r & (RING - 1)][c] = realp(v);
@@ -549,7 +568,7 @@ __global__ __launch_bounds__(256) void back_chase_kernel(int n, int b, int nsw, 
     };
     auto store_rows = [&](int ra, int rb) {
         const int nr = rb - ra;
-        for (int e = tid; e < nr * CT; e += 256) {
+        for (int e = tid; e < nr * CT; e += NT) {
             const int r = ra + e % nr, c = e / nr;
             if (c < ncol) {
                 T v;
@@ -559,32 +578,23 @@ __global__ __launch_bounds__(256) void back_chase_kernel(int n, int b, int nsw, 
             }
         }
     };
-    // V[r][j] of the current group (r relative to the window start)
-    auto vget = [&](int comp, int r, int j, int lg) -> double {
-        const int q = r - j;
-        return (r < lg && q >= 0 && q < b) ? vc[comp][j][q] : 0.0;
-    };
-
-    // Next group's reflectors and T factor are fetched into registers while
-    // the current group's products run (software pipelining).
-    constexpr int VPT = NBS * MAXB / 256, TPT = NBS * NBS / 256;
+    constexpr int VPT = NBS * MAXB / NT, TPT = NBS * NBS / NT;
     T vreg[VPT], treg[TPT];
     auto fetch = [&](int S, int t) {
         const int s0 = S * NBS, s1 = min(nsw, s0 + NBS);
         const T* vsrc = V2 + ((size_t)t * nsw + s0) * b;
 #pragma unroll
         for (int k = 0; k < VPT; ++k) {
-            const int e = tid + 256 * k;
+            const int e = tid + NT * k;
             const int j = e / b, s = s0 + j;
-            // reflector slots past the end of the matrix were never written
             const bool ok = e < NBS * b && s < s1 && s + 1 + t * b < n;
             vreg[k] = ok ? vsrc[e] : zero_of<T>();
         }
         const T* tsrc = Tg + ((size_t)t * nblk + S) * NBS * NBS;
 #pragma unroll
-        for (int k = 0; k < TPT; ++k) treg[k] = tsrc[tid + 256 * k];
+        for (int k = 0; k < TPT; ++k) treg[k] = tsrc[tid + NT * k];
     };
-    auto next_group = [&](int& S, int& t) {  // group order: t ascending within S, S descending
+    auto next_group = [&](int& S, int& t) {
         if (S * NBS + 1 + (t + 1) * b < n) {
             ++t;
         } else {
@@ -592,17 +602,14 @@ __global__ __launch_bounds__(256) void back_chase_kernel(int n, int b, int nsw, 
             t = 0;
         }
     };
-    // The rows a group adds to the window are also fetched one group ahead
-    // (within a sweep block; the window's jump back to the top at the next
-    // block reads rows this workgroup may still hold, so those load in place).
-    constexpr int ZPT = MAXB * CT / 256;
+    constexpr int ZPT = MAXB * CT / NT;
     T zpre[ZPT];
     int pre_a = -1, pre_b = -1;
     auto prefetch_rows = [&](int ra, int rb) {
         const int nr = rb - ra;
 #pragma unroll
         for (int k = 0; k < ZPT; ++k) {
-            const int e = tid + 256 * k;
+            const int e = tid + NT * k;
             zpre[k] = zero_of<T>();
             if (e < nr * CT) {
                 const int r = ra + e % nr, c = e / nr;
@@ -616,7 +623,7 @@ __global__ __launch_bounds__(256) void back_chase_kernel(int n, int b, int nsw, 
         const int nr = pre_b - pre_a;
 #pragma unroll
         for (int k = 0; k < ZPT; ++k) {
-            const int e = tid + 256 * k;
+            const int e = tid + NT * k;
             if (e < nr * CT) {
                 const int r = pre_a + e % nr, c = e / nr;
                 zr[0][r & (RING - 1)][c] = realp(zpre[k]);
@@ -644,18 +651,19 @@ __global__ __launch_bounds__(256) void back_chase_kernel(int n, int b, int nsw, 
             pre_a = pre_b = -1;
             lo = wr0;
             hi = wr1;
-            // this group's reflectors and T (fetched during the previous group)
 #pragma unroll
             for (int k = 0; k < VPT; ++k) {
-                const int e = tid + 256 * k;
+                const int e = tid + NT * k;
                 if (e < NBS * b) {
-                    vc[0][e / b][e % b] = realp(vreg[k]);
-                    if (CX) vc[NC - 1][e / b][e % b] = imagp(vreg[k]);
+                    const int j = e / b, q = e % b;
+                    const bool in = j + q < lg;  // rows past the matrix end hold no reflector entries
+                    vd[0][j][j + q] = in ? realp(vreg[k]) : 0.0;
+                    if (CX) vd[NC - 1][j][j + q] = in ? imagp(vreg[k]) : 0.0;
                 }
             }
 #pragma unroll
             for (int k = 0; k < TPT; ++k) {
-                const int e = tid + 256 * k;
+                const int e = tid + NT * k;
                 tm[0][e / NBS][e % NBS] = realp(treg[k]);
                 if (CX) tm[NC - 1][e / NBS][e % NBS] = imagp(treg[k]);
             }
@@ -664,28 +672,29 @@ __global__ __launch_bounds__(256) void back_chase_kernel(int n, int b, int nsw, 
                 int Sn = S, tn = t;
                 next_group(Sn, tn);
                 if (Sn >= 0) fetch(Sn, tn);
-                if (Sn == S) {  // next group of this block: rows [wr1, next wr1)
+                if (Sn == S) {
                     const int nw1 = min(n, s1 + (t + 1) * b + b);
                     if (nw1 > wr1 && nw1 - wr1 <= MAXB) prefetch_rows(wr1, nw1);
                 }
             }
             const int base = wr0;
-            // ---- W = V^H Z: block jb of NBS/16, inner range split in P parts
+            // ---- W = V^H Z: block jb, inner rows split in PA parts of KA k-steps
             {
                 const int jb = wv % NB1, part = wv / NB1;
-                const int k0 = jb * 16, k1 = min(lg, jb * 16 + 15 + b);
-                const int len = max(k1 - k0, 0);
-                const int chunk = ((len + P - 1) / P + 3) / 4 * 4;
-                const int ka = k0 + part * chunk, kb = min(k1, ka + chunk);
-                dbl4 cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
-                for (int k = ka; k < kb; k += 4) {
-                    const int r = k + lk, j = jb * 16 + li;
-                    const double ar = vget(0, r, j, lg), ai = CX ? -vget(NC - 1, r, j, lg) : 0.0;  // conj(V)
-                    const bool in = r < kb;
-                    const double br = in ? zr[0][(base + r) & (RING - 1)][li] : 0.0;
-                    const double bi = (CX && in) ? zr[NC - 1][(base + r) & (RING - 1)][li] : 0.0;
-                    mma4<T>(cr, ci, in ? ar : 0.0, in ? ai : 0.0, br, bi);
+                const int j = jb * 16 + li;
+                const int rk = jb * 16 + part * KA * 4 + lk;
+                double ar[KA], ai[KA], br[KA], bi[KA];
+#pragma unroll
+                for (int kk = 0; kk < KA; ++kk) {
+                    const int r = rk + 4 * kk;
+                    ar[kk] = vd[0][j][r];
+                    ai[kk] = CX ? -vd[NC - 1][j][r] : 0.0;
+                    br[kk] = zr[0][(base + r) & (RING - 1)][li];
+                    bi[kk] = CX ? zr[NC - 1][(base + r) & (RING - 1)][li] : 0.0;
                 }
+                dbl4 cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
+#pragma unroll
+                for (int kk = 0; kk < KA; ++kk) mma4<T>(cr, ci, ar[kk], ai[kk], br[kk], bi[kk]);
 #pragma unroll
                 for (int rr = 0; rr < 4; ++rr) {
                     wp[0][part][jb * 16 + 4 * rr + lk][li] = cr[rr];
@@ -693,49 +702,57 @@ __global__ __launch_bounds__(256) void back_chase_kernel(int n, int b, int nsw, 
                 }
             }
             __syncthreads();
-            for (int e = tid; e < NBS * CT; e += 256) {
-                const int j = e / CT, c = e % CT;
+            // ---- W1 = T W (T upper triangular), in two parts of the inner range
+            if (wv < 2 * NB1) {
+                const int jb = wv % NB1, part = wv / NB1;
+                double ar[KP], ai[KP], br[KP], bi[KP];
 #pragma unroll
-                for (int comp = 0; comp < NC; ++comp) {
-                    double acc = wp[comp][0][j][c];
-                    for (int q = 1; q < P; ++q) acc += wp[comp][q][j][c];
-                    wp[comp][0][j][c] = acc;
+                for (int kk = 0; kk < KP; ++kk) {
+                    const int ks = part * KP + kk;
+                    const bool on = ks >= 4 * jb;  // T[i][k] = 0 for k < i
+                    const int k = 4 * ks + lk;
+                    ar[kk] = on ? tm[0][jb * 16 + li][k] : 0.0;
+                    ai[kk] = (CX && on) ? tm[NC - 1][jb * 16 + li][k] : 0.0;
+                    double sr = 0.0, si = 0.0;
+#pragma unroll
+                    for (int p = 0; p < PA; ++p) {
+                        sr += wp[0][p][k][li];
+                        if (CX) si += wp[NC - 1][p][k][li];
+                    }
+                    br[kk] = on ? sr : 0.0;
+                    bi[kk] = on ? si : 0.0;
+                }
+                dbl4 cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
+#pragma unroll
+                for (int kk = 0; kk < KP; ++kk) mma4<T>(cr, ci, ar[kk], ai[kk], br[kk], bi[kk]);
+#pragma unroll
+                for (int rr = 0; rr < 4; ++rr) {
+                    w1[0][part][jb * 16 + 4 * rr + lk][li] = cr[rr];
+                    if (CX) w1[NC - 1][part][jb * 16 + 4 * rr + lk][li] = ci[rr];
                 }
             }
             __syncthreads();
-            // ---- W1 = T W (T upper triangular)
-            if (wv < NB1) {
-                const int jb = wv;
-                dbl4 cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
-                for (int k = jb * 16; k < NBS; k += 4) {
-                    const double ar = tm[0][jb * 16 + li][k + lk], ai = CX ? tm[NC - 1][jb * 16 + li][k + lk] : 0.0;
-                    const double br = wp[0][0][k + lk][li], bi = CX ? wp[NC - 1][0][k + lk][li] : 0.0;
-                    mma4<T>(cr, ci, ar, ai, br, bi);
+            // ---- Z <- Z - V W1: one 16-row block of the window per wave
+            if (wv < NRB && wv * 16 < lg) {
+                const int r = wv * 16 + li;
+                double ar[KS], ai[KS], br[KS], bi[KS];
+#pragma unroll
+                for (int ks = 0; ks < KS; ++ks) {
+                    const int j = 4 * ks + lk;
+                    ar[ks] = vd[0][j][r];
+                    ai[ks] = CX ? vd[NC - 1][j][r] : 0.0;
+                    br[ks] = w1[0][0][j][li] + w1[0][1][j][li];
+                    bi[ks] = CX ? w1[NC - 1][0][j][li] + w1[NC - 1][1][j][li] : 0.0;
                 }
+                dbl4 cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
+#pragma unroll
+                for (int ks = 0; ks < KS; ++ks) mma4<T>(cr, ci, ar[ks], ai[ks], br[ks], bi[ks]);
 #pragma unroll
                 for (int rr = 0; rr < 4; ++rr) {
-                    w1[0][jb * 16 + 4 * rr + lk][li] = cr[rr];
-                    if (CX) w1[NC - 1][jb * 16 + 4 * rr + lk][li] = ci[rr];
-                }
-            }
-            __syncthreads();
-            // ---- Z <- Z - V W1, row blocks of 16 over the window
-            const int nrb = (lg + 15) / 16;
-            for (int rb = wv; rb < nrb; rb += 4) {
-                const int ka = max(0, rb * 16 - b + 1) / 4 * 4, kb = min(NBS, rb * 16 + 16);
-                dbl4 cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
-                for (int k = ka; k < kb; k += 4) {
-                    const int r = rb * 16 + li, j = k + lk;
-                    const double ar = vget(0, r, j, lg), ai = CX ? vget(NC - 1, r, j, lg) : 0.0;
-                    const double br = w1[0][j][li], bi = CX ? w1[NC - 1][j][li] : 0.0;
-                    mma4<T>(cr, ci, ar, ai, br, bi);
-                }
-#pragma unroll
-                for (int rr = 0; rr < 4; ++rr) {
-                    const int r = rb * 16 + 4 * rr + lk;
-                    if (r < lg) {
-                        zr[0][(base + r) & (RING - 1)][li] -= cr[rr];
-                        if (CX) zr[NC - 1][(base + r) & (RING - 1)][li] -= ci[rr];
+                    const int rw = wv * 16 + 4 * rr + lk;
+                    if (rw < lg) {
+                        zr[0][(base + rw) & (RING - 1)][li] -= cr[rr];
+                        if (CX) zr[NC - 1][(base + rw) & (RING - 1)][li] -= ci[rr];
                     }
                 }
             }
@@ -798,7 +815,7 @@ int back_chase(const StageCtx& c, const ChaseRefl<T>& R, int nev, T* Z, long ldz
     // algorithmic work: every reflector applied to every column, 4 L nev
     // real flops each (x4 complex): about 2 n^2 nev in total
     KProbe probe(c.st, GEVD_K_BACKCHASE, (is_cplx<T>::value ? 8.0 : 2.0) * (double)R.n * R.n * nev);
-    hipLaunchKernelGGL((back_chase_kernel<T, NBS>), dim3(grid), dim3(256), 0, c.st, R.n, R.b, R.nsw, R.nblk,
+    hipLaunchKernelGGL((back_chase_kernel<T, NBS>), dim3(grid), dim3(512), 0, c.st, R.n, R.b, R.nsw, R.nblk,
                        (const T*)R.V2, (const T*)R.Tg, nev, Z, ldz);
     GEVD_LAUNCH_CHECK();
     return 0;
