@@ -30,6 +30,27 @@ constexpr int MAXB = 64;
 constexpr unsigned long long WAIT_LIMIT_TICKS = 120ull * 100000000ull;
 constexpr int LB = 32;  // independent loads per lane per batch (b = 32: one batch)
 
+// Band entries move between the workgroups of consecutive sweeps, which may
+// sit on different XCDs whose L2 caches are not coherent with each other.
+// They are therefore read and written at system scope: loads bypass the
+// caches and stores are written through to memory, so a task only has to
+// wait for its own stores to complete before it publishes its progress
+// counter, and a waiter reads fresh data without invalidating its L2 (which
+// would also throw away every other workgroup's cached lines on that XCD).
+__device__ inline double band_ld(const double* p) {
+    return __longlong_as_double(
+        __hip_atomic_load(reinterpret_cast<const long long*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM));
+}
+__device__ inline zdouble band_ld(const zdouble* p) { return {band_ld(&p->x), band_ld(&p->y)}; }
+__device__ inline void band_st(double* p, double v) {
+    __hip_atomic_store(reinterpret_cast<long long*>(p), __double_as_longlong(v), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_SYSTEM);
+}
+__device__ inline void band_st(zdouble* p, zdouble v) {
+    band_st(&p->x, v.x);
+    band_st(&p->y, v.y);
+}
+
 __device__ inline int ntasks(int n, int b, int sw) { return (n - 1 - sw + b - 1) / b; }
 
 // Householder reflector for x[0..L-1] (LDS, overwritten by v with v[0] = 1):
@@ -97,8 +118,8 @@ __global__ __launch_bounds__(64) void hb2st_kernel(int n, int b, T* Bw, long ldw
                     // Relaxed polling, with an acquire every 64 polls: the L2
                     // of this XCD is not coherent with the writer's, and a
                     // relaxed load may keep hitting a stale line there until
-                    // an acquire invalidates it.  One acquire fence follows
-                    // once the wait is satisfied.
+                    // an acquire invalidates it.  The band itself is read
+                    // past the caches (band_ld), so no fence follows.
                     while (__hip_atomic_load(&progress[sw - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
                         if ((++spins & 63u) == 0) {
                             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
@@ -116,7 +137,6 @@ __global__ __launch_bounds__(64) void hb2st_kernel(int n, int b, T* Bw, long ldw
                 }
                 __syncthreads();
                 if (stop) return;
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             }
             const int r0 = sw + 1 + t * b;
             const int L = min(b, n - r0);
@@ -134,10 +154,10 @@ __global__ __launch_bounds__(64) void hb2st_kernel(int n, int b, T* Bw, long ldw
                         tmp[k] = zero_of<T>();
                         if (e < ne) {
                             const int i = e % L, j = e / L;
-                            tmp[k] = Bw[IDX(b + i - j, pr0 + j, ldw)];
+                            tmp[k] = band_ld(&Bw[IDX(b + i - j, pr0 + j, ldw)]);
                         } else if (e < ne + nd) {
                             const int f = e - ne, i = f % L, j = f / L;
-                            if (i >= j) tmp[k] = Bw[IDX(i - j, r0 + j, ldw)];
+                            if (i >= j) tmp[k] = band_ld(&Bw[IDX(i - j, r0 + j, ldw)]);
                         }
                     }
 #pragma unroll
@@ -155,12 +175,12 @@ __global__ __launch_bounds__(64) void hb2st_kernel(int n, int b, T* Bw, long ldw
                         }
                     }
                 }
-                if (t == 0 && lane < L) v[lane] = Bw[IDX(1 + lane, sw, ldw)];
+                if (t == 0 && lane < L) v[lane] = band_ld(&Bw[IDX(1 + lane, sw, ldw)]);
                 __syncthreads();
             }
             if (t == 0) {
                 reflect1<T>(v, L, sc);
-                if (lane < L) Bw[IDX(1 + lane, sw, ldw)] = (lane == 0) ? sc[1] : zero_of<T>();
+                if (lane < L) band_st(&Bw[IDX(1 + lane, sw, ldw)], (lane == 0) ? sc[1] : zero_of<T>());
             } else {
                 const T pt = ptau;
                 if (lane < L) {
@@ -186,8 +206,9 @@ __global__ __launch_bounds__(64) void hb2st_kernel(int n, int b, T* Bw, long ldw
                     if (lane < L) {
                         const int i = lane;
                         const T cv = ctau * v[i];
-                        for (int j = 1; j < b; ++j) Bw[IDX(b + i - j, pr0 + j, ldw)] = EL_(i, j) - cv * y[j];
-                        Bw[IDX(b + i, pr0, ldw)] = (i == 0) ? sc[1] : zero_of<T>();
+                        for (int j = 1; j < b; ++j)
+                            band_st(&Bw[IDX(b + i - j, pr0 + j, ldw)], EL_(i, j) - cv * y[j]);
+                        band_st(&Bw[IDX(b + i, pr0, ldw)], (i == 0) ? sc[1] : zero_of<T>());
                     }
                 } else {
                     if (lane == 0) {
@@ -195,7 +216,7 @@ __global__ __launch_bounds__(64) void hb2st_kernel(int n, int b, T* Bw, long ldw
                         sc[0] = zero_of<T>();
                     }
                     if (lane < L)
-                        for (int j = 0; j < b; ++j) Bw[IDX(b + lane - j, pr0 + j, ldw)] = EL_(lane, j);
+                        for (int j = 0; j < b; ++j) band_st(&Bw[IDX(b + lane - j, pr0 + j, ldw)], EL_(lane, j));
                     __syncthreads();
                 }
             }
@@ -217,7 +238,7 @@ __global__ __launch_bounds__(64) void hb2st_kernel(int n, int b, T* Bw, long ldw
                     for (int j = 0; j <= i; ++j) {
                         T x = DL_(i, j) - v[i] * conjg(y[j]) - y[i] * conjg(v[j]);
                         if (i == j) x = from_real<T>(realp(x));
-                        Bw[IDX(i - j, r0 + j, ldw)] = x;
+                        band_st(&Bw[IDX(i - j, r0 + j, ldw)], x);
                     }
                 }
             }
@@ -228,11 +249,11 @@ __global__ __launch_bounds__(64) void hb2st_kernel(int n, int b, T* Bw, long ldw
             __syncthreads();
             if (lane < MAXB) vp[lane] = (lane < L) ? v[lane] : zero_of<T>();
             if (lane == 0) ptau = tau;
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // this wave's band stores, device-wide
+            __builtin_amdgcn_s_waitcnt(0);  // this wave's band stores have reached memory
             __syncthreads();
-            // The counter is stored at system scope: written through, not
-            // left in this XCD's L2 where a waiter on another XCD would see
-            // it late (the fence above already ordered the band stores).
+            // The counter is stored at system scope too: written through,
+            // not left in this XCD's L2 where a waiter on another XCD would
+            // see it late.
             if (lane == 0) __hip_atomic_store(&progress[sw], t + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
         }
     }
@@ -298,7 +319,6 @@ __global__ __launch_bounds__(64 * CW) void hb2st_kernel_wg(int n, int b, T* Bw, 
                 }
                 __syncthreads();
                 if (stop) return;
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             }
             const int r0 = sw + 1 + t * b;
             const int L = min(b, n - r0);
@@ -313,10 +333,10 @@ __global__ __launch_bounds__(64 * CW) void hb2st_kernel_wg(int n, int b, T* Bw, 
                         tmp[k] = zero_of<T>();
                         if (e < ne) {
                             const int i = e % L, j = e / L;
-                            tmp[k] = Bw[IDX(b + i - j, pr0 + j, ldw)];
+                            tmp[k] = band_ld(&Bw[IDX(b + i - j, pr0 + j, ldw)]);
                         } else if (e < ne + nd) {
                             const int f = e - ne, i = f % L, j = f / L;
-                            if (i >= j) tmp[k] = Bw[IDX(i - j, r0 + j, ldw)];
+                            if (i >= j) tmp[k] = band_ld(&Bw[IDX(i - j, r0 + j, ldw)]);
                         }
                     }
 #pragma unroll
@@ -334,13 +354,13 @@ __global__ __launch_bounds__(64 * CW) void hb2st_kernel_wg(int n, int b, T* Bw, 
                         }
                     }
                 }
-                if (t == 0 && tid < L) v[tid] = Bw[IDX(1 + tid, sw, ldw)];
+                if (t == 0 && tid < L) v[tid] = band_ld(&Bw[IDX(1 + tid, sw, ldw)]);
                 __syncthreads();
             }
             const int j0 = wv * q, j1 = min(b, j0 + q);
             if (t == 0) {
                 reflect1<T>(v, L, sc);
-                if (tid < L) Bw[IDX(1 + tid, sw, ldw)] = (tid == 0) ? sc[1] : zero_of<T>();
+                if (tid < L) band_st(&Bw[IDX(1 + tid, sw, ldw)], (tid == 0) ? sc[1] : zero_of<T>());
             } else {
                 if (lane < L) {
                     T acc = zero_of<T>();
@@ -376,8 +396,8 @@ __global__ __launch_bounds__(64 * CW) void hb2st_kernel_wg(int n, int b, T* Bw, 
                     const T ctau = conjg(sc[0]);
                     for (int e = tid; e < L * b; e += NT) {
                         const int i = e % L, j = e / L;
-                        if (j == 0) Bw[IDX(b + i, pr0, ldw)] = (i == 0) ? sc[1] : zero_of<T>();
-                        else Bw[IDX(b + i - j, pr0 + j, ldw)] = EL_(i, j) - ctau * v[i] * y[j];
+                        if (j == 0) band_st(&Bw[IDX(b + i, pr0, ldw)], (i == 0) ? sc[1] : zero_of<T>());
+                        else band_st(&Bw[IDX(b + i - j, pr0 + j, ldw)], EL_(i, j) - ctau * v[i] * y[j]);
                     }
                 } else {
                     if (tid == 0) {
@@ -386,7 +406,7 @@ __global__ __launch_bounds__(64 * CW) void hb2st_kernel_wg(int n, int b, T* Bw, 
                     }
                     for (int e = tid; e < L * b; e += NT) {
                         const int i = e % L, j = e / L;
-                        Bw[IDX(b + i - j, pr0 + j, ldw)] = EL_(i, j);
+                        band_st(&Bw[IDX(b + i - j, pr0 + j, ldw)], EL_(i, j));
                     }
                     __syncthreads();
                 }
@@ -419,7 +439,7 @@ __global__ __launch_bounds__(64 * CW) void hb2st_kernel_wg(int n, int b, T* Bw, 
                     if (i >= j) {
                         T x = DL_(i, j) - v[i] * conjg(y[j]) - y[i] * conjg(v[j]);
                         if (i == j) x = from_real<T>(realp(x));
-                        Bw[IDX(i - j, r0 + j, ldw)] = x;
+                        band_st(&Bw[IDX(i - j, r0 + j, ldw)], x);
                     }
                 }
             }
@@ -429,7 +449,7 @@ __global__ __launch_bounds__(64 * CW) void hb2st_kernel_wg(int n, int b, T* Bw, 
             __syncthreads();
             if (tid < MAXB) vp[tid] = (tid < L) ? v[tid] : zero_of<T>();
             if (tid == 0) ptau = tau;
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            __builtin_amdgcn_s_waitcnt(0);
             __syncthreads();
             if (tid == 0) __hip_atomic_store(&progress[sw], t + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
         }
