@@ -86,6 +86,25 @@ __device__ inline zdouble wave_sum(zdouble v) {
     return {wave_sum(v.x), wave_sum(v.y)};
 }
 
+// System-scope loads and stores of data shared between workgroups of one
+// running kernel: loads bypass the (per-XCD, mutually non-coherent) caches,
+// stores are written through to memory.  A writer that waits for its own
+// stores (s_waitcnt) before it raises a flag needs no cache write-back, and
+// a reader that sees the flag needs no cache invalidation.
+__device__ inline double sys_load(const double* p) {
+    return __longlong_as_double(
+        __hip_atomic_load(reinterpret_cast<const long long*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM));
+}
+__device__ inline zdouble sys_load(const zdouble* p) { return {sys_load(&p->x), sys_load(&p->y)}; }
+__device__ inline void sys_store(double* p, double v) {
+    __hip_atomic_store(reinterpret_cast<long long*>(p), __double_as_longlong(v), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_SYSTEM);
+}
+__device__ inline void sys_store(zdouble* p, zdouble v) {
+    sys_store(&p->x, v.x);
+    sys_store(&p->y, v.y);
+}
+
 // Block-wide sum for blockDim.x == NT (multiple of 64); all threads receive
 // the result.  red must hold NT/64 entries of T.
 template <int NT, typename T>

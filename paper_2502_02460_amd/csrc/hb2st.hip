@@ -32,25 +32,11 @@ constexpr int LB = 32;  // independent loads per lane per batch (b = 32: one bat
 
 // Band entries move between the workgroups of consecutive sweeps, which may
 // sit on different XCDs whose L2 caches are not coherent with each other.
-// They are therefore read and written at system scope: loads bypass the
-// caches and stores are written through to memory, so a task only has to
-// wait for its own stores to complete before it publishes its progress
-// counter, and a waiter reads fresh data without invalidating its L2 (which
-// would also throw away every other workgroup's cached lines on that XCD).
-__device__ inline double band_ld(const double* p) {
-    return __longlong_as_double(
-        __hip_atomic_load(reinterpret_cast<const long long*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM));
-}
-__device__ inline zdouble band_ld(const zdouble* p) { return {band_ld(&p->x), band_ld(&p->y)}; }
-__device__ inline void band_st(double* p, double v) {
-    __hip_atomic_store(reinterpret_cast<long long*>(p), __double_as_longlong(v), __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_SYSTEM);
-}
-__device__ inline void band_st(zdouble* p, zdouble v) {
-    band_st(&p->x, v.x);
-    band_st(&p->y, v.y);
-}
-
+// They are therefore read and written at system scope (sys_load,
+// sys_store): a task only has to wait for its own stores to complete before
+// it publishes its progress counter, and a waiter reads fresh data without
+// invalidating its L2 (which would also throw away every other workgroup's
+// cached lines on that XCD).
 __device__ inline int ntasks(int n, int b, int sw) { return (n - 1 - sw + b - 1) / b; }
 
 // Householder reflector for x[0..L-1] (LDS, overwritten by v with v[0] = 1):
@@ -119,7 +105,7 @@ __global__ __launch_bounds__(64) void hb2st_kernel(int n, int b, T* Bw, long ldw
                     // of this XCD is not coherent with the writer's, and a
                     // relaxed load may keep hitting a stale line there until
                     // an acquire invalidates it.  The band itself is read
-                    // past the caches (band_ld), so no fence follows.
+                    // past the caches (sys_load), so no fence follows.
                     while (__hip_atomic_load(&progress[sw - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
                         if ((++spins & 63u) == 0) {
                             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
@@ -154,10 +140,10 @@ __global__ __launch_bounds__(64) void hb2st_kernel(int n, int b, T* Bw, long ldw
                         tmp[k] = zero_of<T>();
                         if (e < ne) {
                             const int i = e % L, j = e / L;
-                            tmp[k] = band_ld(&Bw[IDX(b + i - j, pr0 + j, ldw)]);
+                            tmp[k] = sys_load(&Bw[IDX(b + i - j, pr0 + j, ldw)]);
                         } else if (e < ne + nd) {
                             const int f = e - ne, i = f % L, j = f / L;
-                            if (i >= j) tmp[k] = band_ld(&Bw[IDX(i - j, r0 + j, ldw)]);
+                            if (i >= j) tmp[k] = sys_load(&Bw[IDX(i - j, r0 + j, ldw)]);
                         }
                     }
 #pragma unroll
@@ -175,12 +161,12 @@ __global__ __launch_bounds__(64) void hb2st_kernel(int n, int b, T* Bw, long ldw
                         }
                     }
                 }
-                if (t == 0 && lane < L) v[lane] = band_ld(&Bw[IDX(1 + lane, sw, ldw)]);
+                if (t == 0 && lane < L) v[lane] = sys_load(&Bw[IDX(1 + lane, sw, ldw)]);
                 __syncthreads();
             }
             if (t == 0) {
                 reflect1<T>(v, L, sc);
-                if (lane < L) band_st(&Bw[IDX(1 + lane, sw, ldw)], (lane == 0) ? sc[1] : zero_of<T>());
+                if (lane < L) sys_store(&Bw[IDX(1 + lane, sw, ldw)], (lane == 0) ? sc[1] : zero_of<T>());
             } else {
                 const T pt = ptau;
                 if (lane < L) {
@@ -207,8 +193,8 @@ __global__ __launch_bounds__(64) void hb2st_kernel(int n, int b, T* Bw, long ldw
                         const int i = lane;
                         const T cv = ctau * v[i];
                         for (int j = 1; j < b; ++j)
-                            band_st(&Bw[IDX(b + i - j, pr0 + j, ldw)], EL_(i, j) - cv * y[j]);
-                        band_st(&Bw[IDX(b + i, pr0, ldw)], (i == 0) ? sc[1] : zero_of<T>());
+                            sys_store(&Bw[IDX(b + i - j, pr0 + j, ldw)], EL_(i, j) - cv * y[j]);
+                        sys_store(&Bw[IDX(b + i, pr0, ldw)], (i == 0) ? sc[1] : zero_of<T>());
                     }
                 } else {
                     if (lane == 0) {
@@ -216,7 +202,7 @@ __global__ __launch_bounds__(64) void hb2st_kernel(int n, int b, T* Bw, long ldw
                         sc[0] = zero_of<T>();
                     }
                     if (lane < L)
-                        for (int j = 0; j < b; ++j) band_st(&Bw[IDX(b + lane - j, pr0 + j, ldw)], EL_(lane, j));
+                        for (int j = 0; j < b; ++j) sys_store(&Bw[IDX(b + lane - j, pr0 + j, ldw)], EL_(lane, j));
                     __syncthreads();
                 }
             }
@@ -238,7 +224,7 @@ __global__ __launch_bounds__(64) void hb2st_kernel(int n, int b, T* Bw, long ldw
                     for (int j = 0; j <= i; ++j) {
                         T x = DL_(i, j) - v[i] * conjg(y[j]) - y[i] * conjg(v[j]);
                         if (i == j) x = from_real<T>(realp(x));
-                        band_st(&Bw[IDX(i - j, r0 + j, ldw)], x);
+                        sys_store(&Bw[IDX(i - j, r0 + j, ldw)], x);
                     }
                 }
             }
@@ -333,10 +319,10 @@ __global__ __launch_bounds__(64 * CW) void hb2st_kernel_wg(int n, int b, T* Bw, 
                         tmp[k] = zero_of<T>();
                         if (e < ne) {
                             const int i = e % L, j = e / L;
-                            tmp[k] = band_ld(&Bw[IDX(b + i - j, pr0 + j, ldw)]);
+                            tmp[k] = sys_load(&Bw[IDX(b + i - j, pr0 + j, ldw)]);
                         } else if (e < ne + nd) {
                             const int f = e - ne, i = f % L, j = f / L;
-                            if (i >= j) tmp[k] = band_ld(&Bw[IDX(i - j, r0 + j, ldw)]);
+                            if (i >= j) tmp[k] = sys_load(&Bw[IDX(i - j, r0 + j, ldw)]);
                         }
                     }
 #pragma unroll
@@ -354,13 +340,13 @@ __global__ __launch_bounds__(64 * CW) void hb2st_kernel_wg(int n, int b, T* Bw, 
                         }
                     }
                 }
-                if (t == 0 && tid < L) v[tid] = band_ld(&Bw[IDX(1 + tid, sw, ldw)]);
+                if (t == 0 && tid < L) v[tid] = sys_load(&Bw[IDX(1 + tid, sw, ldw)]);
                 __syncthreads();
             }
             const int j0 = wv * q, j1 = min(b, j0 + q);
             if (t == 0) {
                 reflect1<T>(v, L, sc);
-                if (tid < L) band_st(&Bw[IDX(1 + tid, sw, ldw)], (tid == 0) ? sc[1] : zero_of<T>());
+                if (tid < L) sys_store(&Bw[IDX(1 + tid, sw, ldw)], (tid == 0) ? sc[1] : zero_of<T>());
             } else {
                 if (lane < L) {
                     T acc = zero_of<T>();
@@ -396,8 +382,8 @@ __global__ __launch_bounds__(64 * CW) void hb2st_kernel_wg(int n, int b, T* Bw, 
                     const T ctau = conjg(sc[0]);
                     for (int e = tid; e < L * b; e += NT) {
                         const int i = e % L, j = e / L;
-                        if (j == 0) band_st(&Bw[IDX(b + i, pr0, ldw)], (i == 0) ? sc[1] : zero_of<T>());
-                        else band_st(&Bw[IDX(b + i - j, pr0 + j, ldw)], EL_(i, j) - ctau * v[i] * y[j]);
+                        if (j == 0) sys_store(&Bw[IDX(b + i, pr0, ldw)], (i == 0) ? sc[1] : zero_of<T>());
+                        else sys_store(&Bw[IDX(b + i - j, pr0 + j, ldw)], EL_(i, j) - ctau * v[i] * y[j]);
                     }
                 } else {
                     if (tid == 0) {
@@ -406,7 +392,7 @@ __global__ __launch_bounds__(64 * CW) void hb2st_kernel_wg(int n, int b, T* Bw, 
                     }
                     for (int e = tid; e < L * b; e += NT) {
                         const int i = e % L, j = e / L;
-                        band_st(&Bw[IDX(b + i - j, pr0 + j, ldw)], EL_(i, j));
+                        sys_store(&Bw[IDX(b + i - j, pr0 + j, ldw)], EL_(i, j));
                     }
                     __syncthreads();
                 }
@@ -439,7 +425,7 @@ __global__ __launch_bounds__(64 * CW) void hb2st_kernel_wg(int n, int b, T* Bw, 
                     if (i >= j) {
                         T x = DL_(i, j) - v[i] * conjg(y[j]) - y[i] * conjg(v[j]);
                         if (i == j) x = from_real<T>(realp(x));
-                        band_st(&Bw[IDX(i - j, r0 + j, ldw)], x);
+                        sys_store(&Bw[IDX(i - j, r0 + j, ldw)], x);
                     }
                 }
             }

@@ -245,7 +245,8 @@ __global__ __launch_bounds__(PCT) void panel_cols(T* P, long lda, int m, int b, 
                     pv = a[i];
                     a[i] = zero_of<T>();
                 }
-            ps->prow[par][j] = pv;
+            sys_store(&ps->prow[par][j], pv);
+            __builtin_amdgcn_s_waitcnt(0);  // stored before this wave reaches the barrier below
         }
         // four interleaved partial sums, added in a fixed order
         T y0 = zero_of<T>(), y1 = zero_of<T>(), y2 = zero_of<T>(), y3 = zero_of<T>();
@@ -262,10 +263,10 @@ __global__ __launch_bounds__(PCT) void panel_cols(T* P, long lda, int m, int b, 
             T t = ysh[0][j];
 #pragma unroll
             for (int q = 1; q < PNW; ++q) t += ysh[q][j];
-            partial[((size_t)par * G + blockIdx.x) * WAVE + j] = t;
-            // grid barrier for column s (the pivot row and the partials were
-            // stored by this wave)
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            sys_store(&partial[((size_t)par * G + blockIdx.x) * WAVE + j], t);
+            // grid barrier for column s; the partials and the pivot row are
+            // stored at system scope and complete before the arrival
+            __builtin_amdgcn_s_waitcnt(0);
             if (j == 0) {
                 const unsigned target = bar_base + (unsigned)(s + 1) * (unsigned)G;
                 __hip_atomic_fetch_add(&ps->bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -285,21 +286,20 @@ __global__ __launch_bounds__(PCT) void panel_cols(T* P, long lda, int m, int b, 
                     }
                     __builtin_amdgcn_s_sleep(1);
                 }
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             }
         }
         __syncthreads();
         if (stop) return;
         // all partials of column s: wave g adds workgroups g, g + PNW, ...
         // (independent loads, four at a time), then the waves' sums in order
-        const T prj = ps->prow[par][j];
+        const T prj = sys_load(&ps->prow[par][j]);
         T acc = zero_of<T>();
         for (int q0 = g; q0 < G; q0 += PNW * 4) {
             T v[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int q = q0 + u * PNW;
-                v[u] = q < G ? partial[((size_t)par * G + q) * WAVE + j] : zero_of<T>();
+                v[u] = q < G ? sys_load(&partial[((size_t)par * G + q) * WAVE + j]) : zero_of<T>();
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u) acc += v[u];
