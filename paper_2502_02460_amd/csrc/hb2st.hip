@@ -28,7 +28,6 @@ constexpr int MAXB = 64;
 // A wait gives up after this much device time (wall clock at 100 MHz):
 // far beyond any legitimate wait, so only a broken invariant reaches it.
 constexpr unsigned long long WAIT_LIMIT_TICKS = 120ull * 100000000ull;
-constexpr int LB = 32;  // independent loads per lane per batch (b = 32: one batch)
 
 // Band entries move between the workgroups of consecutive sweeps, which may
 // sit on different XCDs whose L2 caches are not coherent with each other.
@@ -127,38 +126,27 @@ __global__ __launch_bounds__(64) void hb2st_kernel(int n, int b, T* Bw, long ldw
             const int r0 = sw + 1 + t * b;
             const int L = min(b, n - r0);
             const int pr0 = r0 - b;  // previous block (t > 0: always b rows)
-            // Stage this task's blocks in LDS with batches of independent
-            // loads (one memory latency per batch, not per element): E =
-            // B[r0.., pr0..] (t > 0) and the lower triangle of D = B[r0.., r0..].
+            // Stage this task's blocks in LDS: E = B[r0.., pr0..] (t > 0) and
+            // the lower triangle of D = B[r0.., r0..].  Lanes 0-31 and 32-63
+            // take alternate columns of rows lane % 32 (b <= 32 here): all
+            // loads are issued before the first one is used.
             {
-                const int ne = (t > 0) ? L * b : 0, nd = L * L;
-                for (int base = 0; base < ne + nd; base += 64 * LB) {
-                    T tmp[LB];
+                constexpr int HB = 32;
+                const int i = lane % HB, jh = lane / HB;
+                T te[HB / 2], td[HB / 2];
 #pragma unroll
-                    for (int k = 0; k < LB; ++k) {
-                        const int e = base + lane + 64 * k;
-                        tmp[k] = zero_of<T>();
-                        if (e < ne) {
-                            const int i = e % L, j = e / L;
-                            tmp[k] = sys_load(&Bw[IDX(b + i - j, pr0 + j, ldw)]);
-                        } else if (e < ne + nd) {
-                            const int f = e - ne, i = f % L, j = f / L;
-                            if (i >= j) tmp[k] = sys_load(&Bw[IDX(i - j, r0 + j, ldw)]);
-                        }
-                    }
+                for (int k = 0; k < HB / 2; ++k) {
+                    const int j = jh + 2 * k;
+                    te[k] = (t > 0 && i < L && j < b) ? sys_load(&Bw[IDX(b + i - j, pr0 + j, ldw)]) : zero_of<T>();
+                    td[k] = (i < L && j <= i) ? sys_load(&Bw[IDX(i - j, r0 + j, ldw)]) : zero_of<T>();
+                }
 #pragma unroll
-                    for (int k = 0; k < LB; ++k) {
-                        const int e = base + lane + 64 * k;
-                        if (e < ne) {
-                            const int i = e % L, j = e / L;
-                            EL_(i, j) = tmp[k];
-                        } else if (e < ne + nd) {
-                            const int f = e - ne, i = f % L, j = f / L;
-                            if (i >= j) {
-                                DL_(i, j) = tmp[k];
-                                DL_(j, i) = conjg(tmp[k]);
-                            }
-                        }
+                for (int k = 0; k < HB / 2; ++k) {
+                    const int j = jh + 2 * k;
+                    if (t > 0 && i < L && j < b) EL_(i, j) = te[k];
+                    if (i < L && j <= i) {
+                        DL_(i, j) = td[k];
+                        DL_(j, i) = conjg(td[k]);
                     }
                 }
                 if (t == 0 && lane < L) v[lane] = sys_load(&Bw[IDX(1 + lane, sw, ldw)]);
@@ -252,7 +240,6 @@ __global__ __launch_bounds__(64) void hb2st_kernel(int n, int b, T* Bw, long ldw
 // wave, the four waves split the inner index of each block product into
 // quarters and add their partial sums in a fixed order (deterministic).
 constexpr int CW = 4;  // waves per workgroup
-constexpr int LB4 = 32;  // independent loads per lane per batch (b = 64: one batch)
 
 template <typename T>
 __global__ __launch_bounds__(64 * CW) void hb2st_kernel_wg(int n, int b, T* Bw, long ldw, T* V2, T* tau2, int nsw,
@@ -309,35 +296,26 @@ __global__ __launch_bounds__(64 * CW) void hb2st_kernel_wg(int n, int b, T* Bw, 
             const int r0 = sw + 1 + t * b;
             const int L = min(b, n - r0);
             const int pr0 = r0 - b;
+            // Stage this task's blocks in LDS: E = B[r0.., pr0..] (t > 0) and the
+            // lower triangle of D = B[r0.., r0..].  Lane = row, wave = first
+            // column, stepping by CW columns: all loads are issued before the
+            // first one is used (one memory latency per task).
             {
-                const int ne = (t > 0) ? L * b : 0, nd = L * L;
-                for (int base = 0; base < ne + nd; base += NT * LB4) {
-                    T tmp[LB4];
+                T te[MAXB / CW], td[MAXB / CW];
 #pragma unroll
-                    for (int k = 0; k < LB4; ++k) {
-                        const int e = base + tid + NT * k;
-                        tmp[k] = zero_of<T>();
-                        if (e < ne) {
-                            const int i = e % L, j = e / L;
-                            tmp[k] = sys_load(&Bw[IDX(b + i - j, pr0 + j, ldw)]);
-                        } else if (e < ne + nd) {
-                            const int f = e - ne, i = f % L, j = f / L;
-                            if (i >= j) tmp[k] = sys_load(&Bw[IDX(i - j, r0 + j, ldw)]);
-                        }
-                    }
+                for (int k = 0; k < MAXB / CW; ++k) {
+                    const int j = wv + CW * k;
+                    te[k] = (t > 0 && lane < L && j < b) ? sys_load(&Bw[IDX(b + lane - j, pr0 + j, ldw)])
+                                                         : zero_of<T>();
+                    td[k] = (lane < L && j <= lane) ? sys_load(&Bw[IDX(lane - j, r0 + j, ldw)]) : zero_of<T>();
+                }
 #pragma unroll
-                    for (int k = 0; k < LB4; ++k) {
-                        const int e = base + tid + NT * k;
-                        if (e < ne) {
-                            const int i = e % L, j = e / L;
-                            EL_(i, j) = tmp[k];
-                        } else if (e < ne + nd) {
-                            const int f = e - ne, i = f % L, j = f / L;
-                            if (i >= j) {
-                                DL_(i, j) = tmp[k];
-                                DL_(j, i) = conjg(tmp[k]);
-                            }
-                        }
+                for (int k = 0; k < MAXB / CW; ++k) {
+                    const int j = wv + CW * k;
+                    if (t > 0 && lane < L && j < b) EL_(lane, j) = te[k];
+                    if (lane < L && j <= lane) {
+                        DL_(lane, j) = td[k];
+                        DL_(j, lane) = conjg(td[k]);
                     }
                 }
                 if (t == 0 && tid < L) v[tid] = sys_load(&Bw[IDX(1 + tid, sw, ldw)]);
@@ -380,20 +358,20 @@ __global__ __launch_bounds__(64 * CW) void hb2st_kernel_wg(int n, int b, T* Bw, 
                     }
                     __syncthreads();
                     const T ctau = conjg(sc[0]);
-                    for (int e = tid; e < L * b; e += NT) {
-                        const int i = e % L, j = e / L;
-                        if (j == 0) sys_store(&Bw[IDX(b + i, pr0, ldw)], (i == 0) ? sc[1] : zero_of<T>());
-                        else sys_store(&Bw[IDX(b + i - j, pr0 + j, ldw)], EL_(i, j) - ctau * v[i] * y[j]);
+                    if (lane < L) {
+                        const T cv = ctau * v[lane];
+                        for (int j = wv; j < b; j += CW) {
+                            if (j == 0) sys_store(&Bw[IDX(b + lane, pr0, ldw)], (lane == 0) ? sc[1] : zero_of<T>());
+                            else sys_store(&Bw[IDX(b + lane - j, pr0 + j, ldw)], EL_(lane, j) - cv * y[j]);
+                        }
                     }
                 } else {
                     if (tid == 0) {
                         v[0] = from_real<T>(1.0);
                         sc[0] = zero_of<T>();
                     }
-                    for (int e = tid; e < L * b; e += NT) {
-                        const int i = e % L, j = e / L;
-                        sys_store(&Bw[IDX(b + i - j, pr0 + j, ldw)], EL_(i, j));
-                    }
+                    if (lane < L)
+                        for (int j = wv; j < b; j += CW) sys_store(&Bw[IDX(b + lane - j, pr0 + j, ldw)], EL_(lane, j));
                     __syncthreads();
                 }
             }
@@ -420,12 +398,12 @@ __global__ __launch_bounds__(64 * CW) void hb2st_kernel_wg(int n, int b, T* Bw, 
                     if (lane < L) y[lane] = yl + coef * v[lane];
                 }
                 __syncthreads();
-                for (int e = tid; e < L * L; e += NT) {
-                    const int i = e % L, j = e / L;
-                    if (i >= j) {
-                        T x = DL_(i, j) - v[i] * conjg(y[j]) - y[i] * conjg(v[j]);
-                        if (i == j) x = from_real<T>(realp(x));
-                        sys_store(&Bw[IDX(i - j, r0 + j, ldw)], x);
+                if (lane < L) {
+                    const T vi = v[lane], yi = y[lane];
+                    for (int j = wv; j <= lane; j += CW) {
+                        T x = DL_(lane, j) - vi * conjg(y[j]) - yi * conjg(v[j]);
+                        if (lane == j) x = from_real<T>(realp(x));
+                        sys_store(&Bw[IDX(lane - j, r0 + j, ldw)], x);
                     }
                 }
             }
