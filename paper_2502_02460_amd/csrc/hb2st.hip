@@ -255,7 +255,6 @@ __global__ __launch_bounds__(64 * CW) void hb2st_kernel_wg(int n, int b, T* Bw, 
     __shared__ int sw_s, stop;
     const int tid = threadIdx.x, lane = tid % WAVE, wv = tid / WAVE;
     constexpr int NT = 64 * CW;
-    const int q = (b + CW - 1) / CW;  // inner-index quarter
 #define EL_(i, j) Eb[(i) * ldl + (j)]
 #define DL_(i, j) Db[(i) * ldl + (j)]
 
@@ -296,53 +295,59 @@ __global__ __launch_bounds__(64 * CW) void hb2st_kernel_wg(int n, int b, T* Bw, 
             const int r0 = sw + 1 + t * b;
             const int L = min(b, n - r0);
             const int pr0 = r0 - b;
-            // Stage this task's blocks in LDS: E = B[r0.., pr0..] (t > 0) and the
-            // lower triangle of D = B[r0.., r0..].  Lane = row, wave = first
-            // column, stepping by CW columns: all loads are issued before the
-            // first one is used (one memory latency per task).
-            {
-                T te[MAXB / CW], td[MAXB / CW];
+            // Stage this task's blocks: E = B[r0.., pr0..] (t > 0) and the lower
+            // triangle of D = B[r0.., r0..].  Lane = row, wave = first column,
+            // stepping by CW columns; all loads are issued before the first
+            // one is used (one memory latency per task).  E stays in
+            // registers; D also goes to LDS, mirrored, for its matrix-vector
+            // product.
+            constexpr int KW = MAXB / CW;  // columns per lane
+            T te[KW], td[KW];
 #pragma unroll
-                for (int k = 0; k < MAXB / CW; ++k) {
-                    const int j = wv + CW * k;
-                    te[k] = (t > 0 && lane < L && j < b) ? sys_load(&Bw[IDX(b + lane - j, pr0 + j, ldw)])
-                                                         : zero_of<T>();
-                    td[k] = (lane < L && j <= lane) ? sys_load(&Bw[IDX(lane - j, r0 + j, ldw)]) : zero_of<T>();
-                }
-#pragma unroll
-                for (int k = 0; k < MAXB / CW; ++k) {
-                    const int j = wv + CW * k;
-                    if (t > 0 && lane < L && j < b) EL_(lane, j) = te[k];
-                    if (lane < L && j <= lane) {
-                        DL_(lane, j) = td[k];
-                        DL_(j, lane) = conjg(td[k]);
-                    }
-                }
-                if (t == 0 && tid < L) v[tid] = sys_load(&Bw[IDX(1 + tid, sw, ldw)]);
-                __syncthreads();
+            for (int k = 0; k < KW; ++k) {
+                const int j = wv + CW * k;
+                te[k] = (t > 0 && lane < L && j < b) ? sys_load(&Bw[IDX(b + lane - j, pr0 + j, ldw)]) : zero_of<T>();
+                td[k] = (lane < L && j <= lane) ? sys_load(&Bw[IDX(lane - j, r0 + j, ldw)]) : zero_of<T>();
             }
-            const int j0 = wv * q, j1 = min(b, j0 + q);
+#pragma unroll
+            for (int k = 0; k < KW; ++k) {
+                const int j = wv + CW * k;
+                if (lane < L && j <= lane) {
+                    DL_(lane, j) = td[k];
+                    DL_(j, lane) = conjg(td[k]);
+                }
+            }
+            if (t == 0 && tid < L) v[tid] = sys_load(&Bw[IDX(1 + tid, sw, ldw)]);
+            __syncthreads();
             if (t == 0) {
                 reflect1<T>(v, L, sc);
                 if (tid < L) sys_store(&Bw[IDX(1 + tid, sw, ldw)], (tid == 0) ? sc[1] : zero_of<T>());
             } else {
-                if (lane < L) {
+                // E <- E (I - ptau vp vp^H), rows in registers; column 0 is the
+                // next reflector's source
+                {
                     T acc = zero_of<T>();
-                    for (int j = j0; j < j1; ++j) acc += EL_(lane, j) * vp[j];
+#pragma unroll
+                    for (int k = 0; k < KW; ++k) acc += te[k] * vp[wv + CW * k];
                     part[wv][lane] = acc;
                 }
                 __syncthreads();
-                if (lane < L) {
+                {
                     T acc = part[0][lane];
 #pragma unroll
                     for (int w = 1; w < CW; ++w) acc += part[w][lane];
                     const T pa = ptau * acc;
-                    for (int j = j0; j < j1; ++j) EL_(lane, j) -= pa * conjg(vp[j]);
-                    if (j0 == 0) v[lane] = EL_(lane, 0);
+#pragma unroll
+                    for (int k = 0; k < KW; ++k) te[k] -= pa * conjg(vp[wv + CW * k]);
                 }
-                __syncthreads();
+                if (wv == 0) v[lane] = (lane < L) ? te[0] : zero_of<T>();
                 if (L >= 2) {
+#pragma unroll
+                    for (int k = 0; k < KW; ++k)
+                        if (lane < L && wv + CW * k < b) EL_(lane, wv + CW * k) = te[k];
+                    __syncthreads();
                     reflect1<T>(v, L, sc);
+                    // y_j = v^H E[:, j]: lane = column, rows split over the waves
                     const int qi = (L + CW - 1) / CW, i0 = wv * qi, i1 = min(L, i0 + qi);
                     if (lane < b) {
                         T acc = zero_of<T>();
@@ -360,27 +365,40 @@ __global__ __launch_bounds__(64 * CW) void hb2st_kernel_wg(int n, int b, T* Bw, 
                     const T ctau = conjg(sc[0]);
                     if (lane < L) {
                         const T cv = ctau * v[lane];
-                        for (int j = wv; j < b; j += CW) {
+#pragma unroll
+                        for (int k = 0; k < KW; ++k) {
+                            const int j = wv + CW * k;
                             if (j == 0) sys_store(&Bw[IDX(b + lane, pr0, ldw)], (lane == 0) ? sc[1] : zero_of<T>());
-                            else sys_store(&Bw[IDX(b + lane - j, pr0 + j, ldw)], EL_(lane, j) - cv * y[j]);
+                            else if (j < b) sys_store(&Bw[IDX(b + lane - j, pr0 + j, ldw)], te[k] - cv * y[j]);
                         }
                     }
                 } else {
+                    __syncthreads();
                     if (tid == 0) {
                         v[0] = from_real<T>(1.0);
                         sc[0] = zero_of<T>();
                     }
-                    if (lane < L)
-                        for (int j = wv; j < b; j += CW) sys_store(&Bw[IDX(b + lane - j, pr0 + j, ldw)], EL_(lane, j));
+                    if (lane < L) {
+#pragma unroll
+                        for (int k = 0; k < KW; ++k) {
+                            const int j = wv + CW * k;
+                            if (j < b) sys_store(&Bw[IDX(b + lane - j, pr0 + j, ldw)], te[k]);
+                        }
+                    }
                     __syncthreads();
                 }
             }
+            // two-sided update of the diagonal block: y = tau D v,
+            // w = y - 1/2 tau (y^H v) v, D <- D - v w^H - w v^H
             const T tau = sc[0];
             if (!is_zero(tau)) {
-                const int qj = (L + CW - 1) / CW, c0 = wv * qj, c1 = min(L, c0 + qj);
                 if (lane < L) {
                     T acc = zero_of<T>();
-                    for (int j = c0; j < c1; ++j) acc += DL_(lane, j) * v[j];
+#pragma unroll
+                    for (int k = 0; k < KW; ++k) {
+                        const int j = wv + CW * k;
+                        if (j < L) acc += DL_(lane, j) * v[j];
+                    }
                     part[wv][lane] = acc;
                 }
                 __syncthreads();
@@ -400,10 +418,14 @@ __global__ __launch_bounds__(64 * CW) void hb2st_kernel_wg(int n, int b, T* Bw, 
                 __syncthreads();
                 if (lane < L) {
                     const T vi = v[lane], yi = y[lane];
-                    for (int j = wv; j <= lane; j += CW) {
-                        T x = DL_(lane, j) - vi * conjg(y[j]) - yi * conjg(v[j]);
-                        if (lane == j) x = from_real<T>(realp(x));
-                        sys_store(&Bw[IDX(lane - j, r0 + j, ldw)], x);
+#pragma unroll
+                    for (int k = 0; k < KW; ++k) {
+                        const int j = wv + CW * k;
+                        if (j <= lane) {
+                            T x = td[k] - vi * conjg(y[j]) - yi * conjg(v[j]);
+                            if (lane == j) x = from_real<T>(realp(x));
+                            sys_store(&Bw[IDX(lane - j, r0 + j, ldw)], x);
+                        }
                     }
                 }
             }
