@@ -398,6 +398,11 @@ struct Carve {
 };
 
 constexpr int SK = 4;  // split of the long inner dimension in panel products
+// The b x b products over the panel's m rows (V^H V, V^H W) are a single
+// output tile: their inner dimension is split into chunks of about 128 rows
+// so that they fill the device (partials added in a fixed order).
+constexpr int SKS_MAX = 256;
+int sk_small(int m) { return std::max(1, std::min(SKS_MAX, (m + 127) / 128)); }
 
 int count_panels(int n, int b) {
     int np = 0;
@@ -423,7 +428,7 @@ size_t carve_ws(char* base, int n, int b, He2hbWs<T>* w) {
     t.G = c.take<T>((size_t)b * b);
     t.M1 = c.take<T>((size_t)b * b);
     t.M2 = c.take<T>((size_t)b * b);
-    t.skS = c.take<T>((size_t)SK * b * b);
+    t.skS = c.take<T>((size_t)SKS_MAX * b * b);
     const size_t nwg = (size_t)(n + PT - 1) / PT + 1;
     t.partialT = c.take<T>(2 * nwg * (MAXB + 1));
     t.partialD = c.take<double>(nwg);
@@ -487,8 +492,8 @@ int he2hb(const StageCtx& c, int n, T* A, long lda, BandRefl<T>& R, T* Bd, long 
             }
         }
         // T factor from G = V^H V
-        if ((rc = gemm<T>(st, OP_C, OP_N, b, b, m, one, Vp, m, Vp, m, zero, w.G, b, K_FULL, T_ALL, Batch(), SK,
-                          w.skS)))
+        if ((rc = gemm<T>(st, OP_C, OP_N, b, b, m, one, Vp, m, Vp, m, zero, w.G, b, K_FULL, T_ALL, Batch(),
+                          sk_small(m), w.skS)))
             return rc;
         {
             KProbe probe(st, GEVD_K_OTHER, 0.0);
@@ -510,8 +515,8 @@ int he2hb(const StageCtx& c, int n, T* A, long lda, BandRefl<T>& R, T* Bd, long 
                           Batch(), m >= 2048 ? SK : 1, w.skY)))
             return rc;
         if ((rc = gemm<T>(st, OP_N, OP_N, m, b, b, one, w.Y, m, Tp, b, zero, Wb, m, K_B_UPPER))) return rc;  // X
-        if ((rc = gemm<T>(st, OP_C, OP_N, b, b, m, one, Vp, m, Wb, m, zero, w.M1, b, K_FULL, T_ALL, Batch(), SK,
-                          w.skS)))
+        if ((rc = gemm<T>(st, OP_C, OP_N, b, b, m, one, Vp, m, Wb, m, zero, w.M1, b, K_FULL, T_ALL, Batch(),
+                          sk_small(m), w.skS)))
             return rc;
         if ((rc = gemm<T>(st, OP_C, OP_N, b, b, b, one, Tp, b, w.M1, b, zero, w.M2, b, K_A_LOWER))) return rc;
         if ((rc = gemm<T>(st, OP_N, OP_N, m, b, b, mhalf, Vp, m, w.M2, b, one, Wb, m))) return rc;  // W
