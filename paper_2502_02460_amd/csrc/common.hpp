@@ -77,6 +77,10 @@ template <> struct is_cplx<zdouble> { static constexpr bool value = true; };
 // Wave size on CDNA.
 constexpr int WAVE = 64;
 
+// Lane exchange (xor of the lane index) for the scalar types.
+__device__ inline double shfl_xor_s(double v, int m) { return __shfl_xor(v, m, 64); }
+__device__ inline zdouble shfl_xor_s(zdouble v, int m) { return {__shfl_xor(v.x, m, 64), __shfl_xor(v.y, m, 64)}; }
+
 // Sum over a 64-lane wavefront (all lanes receive the result).
 __device__ inline double wave_sum(double v) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);

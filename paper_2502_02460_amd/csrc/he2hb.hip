@@ -345,26 +345,31 @@ __global__ __launch_bounds__(PCT) void panel_cols(T* P, long lda, int m, int b, 
 }
 
 // T (b x b upper) of Q = H_0 ... H_{b-1} = I - V T V^H from the Gram matrix
-// G = V^H V: T[s, s] = tau_s, T[0:s, s] = -tau_s T[0:s, 0:s] G[0:s, s].
+// G = V^H V: T[s, s] = tau_s, T[0:s, s] = -tau_s T[0:s, 0:s] G[0:s, s].  G is
+// staged in LDS; four lanes share each row's dot product (strided quarters
+// of the inner range, added in a fixed order with two lane exchanges).
+constexpr int TFT = 4 * MAXB;
 template <typename T>
-__global__ __launch_bounds__(MAXB) void tfactor_kernel(int b, const T* G, const PanelScratch<T>* ps, T* Tf) {
+__global__ __launch_bounds__(TFT) void tfactor_kernel(int b, const T* G, const PanelScratch<T>* ps, T* Tf) {
     __shared__ T t[MAXB][MAXB + 1];
-    const int i = threadIdx.x;
+    __shared__ T g[MAXB][MAXB + 1];
+    const int tid = threadIdx.x, i = tid / 4, q = tid % 4;
+    for (int e = tid; e < b * b; e += TFT) g[e % b][e / b] = G[e];
+    for (int e = tid; e < MAXB * MAXB; e += TFT) t[e / MAXB][e % MAXB] = zero_of<T>();
+    __syncthreads();
     for (int s = 0; s < b; ++s) {
-        const T ts = ps->tau[s];
-        if (i < s) {
-            T acc = zero_of<T>();
-            for (int l = i; l < s; ++l) acc += t[i][l] * G[IDX(l, s, b)];
-            t[i][s] = -(ts * acc);
-        } else if (i == s) {
-            t[i][s] = ts;
-        } else if (i < b) {
-            t[i][s] = zero_of<T>();
+        T acc = zero_of<T>();
+        if (i < s)
+            for (int l = i + q; l < s; l += 4) acc += t[i][l] * g[l][s];
+        acc += shfl_xor_s(acc, 1);
+        acc += shfl_xor_s(acc, 2);
+        if (q == 0) {
+            if (i < s) t[i][s] = -(ps->tau[s] * acc);
+            else if (i == s) t[i][s] = ps->tau[s];
         }
         __syncthreads();
     }
-    if (i < b)
-        for (int s = 0; s < b; ++s) Tf[IDX(i, s, b)] = t[i][s];
+    for (int e = tid; e < b * b; e += TFT) Tf[e] = t[e % b][e / b];
 }
 
 // Band in lower band storage from the reduced A: columns of processed panels
@@ -497,7 +502,7 @@ int he2hb(const StageCtx& c, int n, T* A, long lda, BandRefl<T>& R, T* Bd, long 
             return rc;
         {
             KProbe probe(st, GEVD_K_OTHER, 0.0);
-            hipLaunchKernelGGL(tfactor_kernel<T>, dim3(1), dim3(MAXB), 0, st, b, (const T*)w.G,
+            hipLaunchKernelGGL(tfactor_kernel<T>, dim3(1), dim3(TFT), 0, st, b, (const T*)w.G,
                                (const PanelScratch<T>*)w.ps, Tp);
         }
         GEVD_LAUNCH_CHECK();

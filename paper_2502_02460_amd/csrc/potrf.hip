@@ -49,11 +49,14 @@ __global__ __launch_bounds__(NTD) void potrf_diag_kernel(int jb, T* S, long lds,
         const double ukk = realp(a[k][k]);
         for (int c = k + 1 + t; c < jb; c += NTD) a[k][c] = div_r(a[k][c], ukk);
         __syncthreads();
-        // trailing: a[r][c] -= conj(a[k][r]) a[k][c], k < r <= c
-        const int m = jb - k - 1;
-        for (int e = t; e < m * m; e += NTD) {
-            int r = k + 1 + e % m, c = k + 1 + e / m;
-            if (r <= c) a[r][c] -= conjg(a[k][r]) * a[k][c];
+        // trailing: a[r][c] -= conj(a[k][r]) a[k][c], k < r <= c (lane = row,
+        // the four waves take every fourth column)
+        {
+            const int r = t % NB;
+            if (r > k && r < jb) {
+                const T akr = conjg(a[k][r]);
+                for (int c = r + (t / NB + NB - r % 4) % 4; c < jb; c += 4) a[r][c] -= akr * a[k][c];
+            }
         }
         __syncthreads();
     }
@@ -62,17 +65,28 @@ __global__ __launch_bounds__(NTD) void potrf_diag_kernel(int jb, T* S, long lds,
         int r = e % jb, c = e / jb;
         if (r <= c) S[IDX(r, c, lds)] = a[r][c];
     }
-    // inverse by columns: thread c solves U x = e_c
-    if (t < jb) {
-        const int c = t;  // this thread owns column c of the inverse
-        for (int i = c + 1; i < NB; ++i) x[i][c] = zero_of<T>();
-        x[c][c] = from_real<T>(1.0 / realp(a[c][c]));
-        for (int i = c - 1; i >= 0; --i) {
-            T s = zero_of<T>();
-            for (int l = i + 1; l <= c; ++l) s += a[i][l] * x[l][c];
-            x[i][c] = div_r(-s, realp(a[i][i]));
+    // inverse by columns: four lanes solve U x = e_c for column c, each
+    // summing every fourth term; the partial sums are added in a fixed order
+    {
+        const int c = t / 4, q = t % 4;
+        if (c < jb) {
+            if (q == 0) {
+                for (int i = c + 1; i < NB; ++i) x[i][c] = zero_of<T>();
+                x[c][c] = from_real<T>(1.0 / realp(a[c][c]));
+            }
         }
-        for (int i = 0; i < jb; ++i) Winv[IDX(i, c, NB)] = x[i][c];
+        for (int i = NB - 2; i >= 0; --i) {
+            // rows run from the bottom for every column at once (rows i >= c
+            // are fixed already), so the loop bound stays uniform
+            T sum = zero_of<T>();
+            if (c < jb && i < c)
+                for (int l = i + 1 + q; l <= c; l += 4) sum += a[i][l] * x[l][c];
+            sum += shfl_xor_s(sum, 1);
+            sum += shfl_xor_s(sum, 2);
+            if (c < jb && i < c && q == 0) x[i][c] = div_r(-sum, realp(a[i][i]));
+        }
+        if (c < jb && q == 0)
+            for (int i = 0; i < jb; ++i) Winv[IDX(i, c, NB)] = x[i][c];
     }
 }
 
