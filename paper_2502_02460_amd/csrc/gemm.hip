@@ -8,10 +8,12 @@
 // triangle is never read) and by clipping the inner-dimension range per
 // output tile, so triangular products cost what their nonzeros cost.
 //
-// Tiling: a 256-thread workgroup (4 wave64s) owns a 64 x 64 output tile;
-// each wave owns 32 x 32 as 2 x 2 MFMA blocks of 16 x 16.  The inner
-// dimension advances in slabs of 16 staged through LDS (double-buffered,
-// one barrier per slab).  The MFMA is issued as D = op(B)^T op(A)^T so that
+// Tiling: a workgroup of 4 wave64s owns a 64 x 64 output tile, each wave
+// 32 x 32 as 2 x 2 MFMA blocks of 16 x 16; large products use 8 waves on a
+// 128 x 128 tile (each wave 64 x 32), which halves the operand traffic per
+// flop, and products with one side of at most 64 use 8 waves on 128 x 64 or
+// 64 x 128.  The inner dimension advances in slabs of 16 staged through LDS
+// (double-buffered, one barrier per slab).  The MFMA is issued as D = op(B)^T op(A)^T so that
 // 16 lanes of a register hold 16 consecutive rows of one column of C: every
 // store instruction writes 128-byte column segments of the column-major C.
 // Complex products use four real MFMAs per complex k-step (re*re - im*im,
@@ -121,16 +123,17 @@ __device__ inline void tile_of(int bid, int nblocks, int tiles_m, bool swizzle, 
     tj = r / gm;
 }
 
-// Workgroup tile BM x BN = (2 WM) x (2 WN): 4 waves in a 2 x 2 layout, each
-// wave owns WM x WN as (WM/16) x (WN/16) MFMA blocks.
-template <typename T, typename CT, int OPA, int OPB, int WM, int WN>
-__global__ __launch_bounds__(NT) void gemm_kernel(GemmP<T> p) {
+// Workgroup tile BM x BN = (WGM WM) x (WGN WN): WGM x WGN waves, each wave
+// owns WM x WN as (WM/16) x (WN/16) MFMA blocks.
+template <typename T, typename CT, int OPA, int OPB, int WM, int WN, int WGM = 2, int WGN = 2>
+__global__ __launch_bounds__(WAVE * WGM * WGN) void gemm_kernel(GemmP<T> p) {
     typedef typename Acc<CT>::type AccT;
     constexpr bool CX = is_cplx<T>::value;
     constexpr int NC = CX ? 2 : 1;
-    constexpr int BM = 2 * WM, BN = 2 * WN;
+    constexpr int NTK = WAVE * WGM * WGN;  // threads
+    constexpr int BM = WGM * WM, BN = WGN * WN;
     constexpr int FA = WM / 16, FB = WN / 16;  // MFMA blocks per wave
-    constexpr int LA = BM * BK / NT, LB = BN * BK / NT;  // elements loaded per thread
+    constexpr int LA = BM * BK / NTK, LB = BN * BK / NTK;  // elements loaded per thread
     __shared__ CT sA[NC][2][BK][BM + 4];
     __shared__ CT sB[NC][2][BK][BN + 4];
 
@@ -160,7 +163,7 @@ __global__ __launch_bounds__(NT) void gemm_kernel(GemmP<T> p) {
 
     const int t = threadIdx.x;
     const int lane = t % WAVE, w = t / WAVE;
-    const int wm = w % 2, wn = w / 2;
+    const int wm = w % WGM, wn = w / WGM;
 
     AccT accR[FA][FB], accI[FA][FB];
 #pragma unroll
@@ -183,7 +186,7 @@ __global__ __launch_bounds__(NT) void gemm_kernel(GemmP<T> p) {
         const bool herm_up = p.kmode == K_A_HERM_LOWER && i0 + BM - 1 < kt;
 #pragma unroll
         for (int r = 0; r < LA; ++r) {
-            const int e = t + r * NT;
+            const int e = t + r * NTK;
             int ii, ll;
             if (OPA == OP_N && !herm_up) { ii = e % BM; ll = e / BM; }
             else { ii = e / BK; ll = e % BK; }
@@ -191,7 +194,7 @@ __global__ __launch_bounds__(NT) void gemm_kernel(GemmP<T> p) {
         }
 #pragma unroll
         for (int r = 0; r < LB; ++r) {
-            const int e = t + r * NT;
+            const int e = t + r * NTK;
             int jj, ll;
             if (OPB == OP_N) { ll = e % BK; jj = e / BK; }
             else { jj = e % BN; ll = e / BN; }
@@ -202,7 +205,7 @@ __global__ __launch_bounds__(NT) void gemm_kernel(GemmP<T> p) {
         const bool herm_up = p.kmode == K_A_HERM_LOWER && i0 + BM - 1 < kt;
 #pragma unroll
         for (int r = 0; r < LA; ++r) {
-            const int e = t + r * NT;
+            const int e = t + r * NTK;
             int ii, ll;
             if (OPA == OP_N && !herm_up) { ii = e % BM; ll = e / BM; }
             else { ii = e / BK; ll = e % BK; }
@@ -211,7 +214,7 @@ __global__ __launch_bounds__(NT) void gemm_kernel(GemmP<T> p) {
         }
 #pragma unroll
         for (int r = 0; r < LB; ++r) {
-            const int e = t + r * NT;
+            const int e = t + r * NTK;
             int jj, ll;
             if (OPB == OP_N) { ll = e % BK; jj = e / BK; }
             else { jj = e % BN; ll = e / BN; }
@@ -336,6 +339,9 @@ void launch_c(hipStream_t st, const GemmP<T>& p, dim3 grid, int cfg) {
         case 3: hipLaunchKernelGGL((gemm_kernel<T, CT, OPA, OPB, 64, 64>), grid, dim3(NT), 0, st, p); break;
         case 4: hipLaunchKernelGGL((gemm_kernel<T, CT, OPA, OPB, 32, 16>), grid, dim3(NT), 0, st, p); break;
         case 5: hipLaunchKernelGGL((gemm_kernel<T, CT, OPA, OPB, 16, 32>), grid, dim3(NT), 0, st, p); break;
+        case 6: hipLaunchKernelGGL((gemm_kernel<T, CT, OPA, OPB, 64, 32, 2, 4>), grid, dim3(8 * WAVE), 0, st, p); break;
+        case 7: hipLaunchKernelGGL((gemm_kernel<T, CT, OPA, OPB, 32, 32, 4, 2>), grid, dim3(8 * WAVE), 0, st, p); break;
+        case 8: hipLaunchKernelGGL((gemm_kernel<T, CT, OPA, OPB, 32, 32, 2, 4>), grid, dim3(8 * WAVE), 0, st, p); break;
         default: hipLaunchKernelGGL((gemm_kernel<T, CT, OPA, OPB, 32, 32>), grid, dim3(NT), 0, st, p); break;
     }
 }
@@ -354,23 +360,32 @@ void launch_b(hipStream_t st, int opB, const GemmP<T>& p, dim3 grid, int cfg) {
 }
 
 // Workgroup tile for a product: 0 = 64x64, 1 = 128x64, 2 = 64x128,
-// 3 = 128x128, 4 = 64x32 (outputs at most 32 columns wide), 5 = 32x64 (at
-// most 32 rows).  GEVD_GEMM_TILE forces one (for measurements).
-constexpr int TILE_BM[6] = {64, 128, 64, 128, 64, 32};
-constexpr int TILE_BN[6] = {64, 64, 128, 128, 32, 64};
+// 3 = 128x128 (four waves each), 4 = 64x32 (outputs at most 32 columns
+// wide), 5 = 32x64 (at most 32 rows); eight waves: 6 = 128x128, 7 = 128x64,
+// 8 = 64x128.  GEVD_GEMM_TILE forces one (for measurements).
+constexpr int NTILE = 9;
+constexpr int TILE_BM[NTILE] = {64, 128, 64, 128, 64, 32, 128, 128, 64};
+constexpr int TILE_BN[NTILE] = {64, 64, 128, 128, 32, 64, 128, 64, 128};
 int g_tile_override = -2;  // -2: not read yet, -1: none
-int pick_tile(int m, int n, int k, bool cx) {
+// Measured on gfx950 (FP64, n = 16384 class shapes): the eight-wave
+// 128 x 128 tile runs square products about 20 % faster than 64 x 64 (real
+// and complex) and rank-2k updates as fast or faster; 128 x 64 and 64 x 128
+// win for outputs 64 wide.  They need enough tiles to fill the 256 CUs (one
+// such workgroup per CU), so medium products keep 64 x 64.
+int pick_tile(int m, int n, bool cx, int splitk, int batch, int tmode) {
     if (g_tile_override == -2) {
         const char* e = getenv("GEVD_GEMM_TILE");
         g_tile_override = e ? atoi(e) : -1;
     }
-    if (g_tile_override >= 0 && g_tile_override <= 5) return (cx && g_tile_override == 3) ? 1 : g_tile_override;
-    (void)k;
-    (void)cx;
-    // measured on gfx950: 64 x 64 is fastest for the solver's square-ish
-    // shapes; a skinny output would leave half of each 64-wide tile idle
+    if (g_tile_override >= 0 && g_tile_override < NTILE) return (cx && g_tile_override == 3) ? 1 : g_tile_override;
     if (n <= 32 && m > 32) return 4;
     if (m <= 32 && n > 32) return 5;
+    const long long par = (long long)splitk * batch;
+    const long long tm = (m + 127) / 128, tn = (n + 127) / 128;
+    const bool tri = tmode != T_ALL;
+    if (m > 64 && n > 64 && tm * tn * par / (tri ? 2 : 1) >= 512) return 6;
+    if (m <= 64 && n > 64 && tn * par >= 256) return 8;
+    if (n <= 64 && m > 64 && tm * par >= 256) return 7;
     return 0;
 }
 
@@ -427,7 +442,7 @@ int gemm(hipStream_t st, int opA, int opB, int m, int n, int k, T alpha, const T
     p.A = A; p.lda = lda; p.B = B; p.ldb = ldb; p.C = C; p.ldc = ldc;
     p.alpha = alpha; p.beta = beta;
     p.kmode = kmode; p.tmode = tmode;
-    const int cfg = pick_tile(m, n, k, is_cplx<T>::value);
+    const int cfg = pick_tile(m, n, is_cplx<T>::value, splitk, batch.count, tmode);
     const int bm = TILE_BM[cfg], bn = TILE_BN[cfg];
     p.bm = bm;
     p.bn = bn;
