@@ -467,8 +467,8 @@ __global__ void extract_tridiag(int n, const T* Bw, long ldw, double* d, double*
 // group's rows in an LDS ring of 128 rows (a group spans at most 127 rows;
 // consecutive groups slide by b).  V is held dense in LDS (zeros outside the
 // staircase, rows padded against bank conflicts), so every product is a
-// fixed-length chain of MFMAs whose operands are loaded into registers
-// first: W's 16-row blocks with their inner range split over the waves
+// fixed-length chain of MFMAs (three per complex k-step) whose operands
+// are loaded into registers first: W's 16-row blocks with their inner range split over the waves
 // (partials added in a fixed order), T W in two halves of its inner range,
 // and one 16-row block of the window per wave for Z - V W.
 // ---------------------------------------------------------------------------
@@ -522,15 +522,23 @@ __global__ __launch_bounds__(256) void chase_tfactor_kernel(int n, int b, int ns
     for (int e = tid; e < NBS * NBS; e += 256) out[e] = Tm[e / NBS][e % NBS];  // row-major
 }
 
+// 16 x 16 block accumulator on the FP64 matrix cores: one MFMA per k-step
+// for real data; for complex data three (Gauss: ar br, ai bi and
+// (ar + ai)(br + bi)), with the real and imaginary parts formed once at the
+// end instead of four MFMAs per k-step.
 template <typename T>
-__device__ inline void mma4(dbl4& cr, dbl4& ci, double ar, double ai, double br, double bi) {
-    cr = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, br, cr, 0, 0, 0);
-    if constexpr (is_cplx<T>::value) {
-        cr = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai, bi, cr, 0, 0, 0);
-        ci = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, bi, ci, 0, 0, 0);
-        ci = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, br, ci, 0, 0, 0);
+struct BlockAcc {
+    dbl4 p1 = {0, 0, 0, 0}, p2 = {0, 0, 0, 0}, p3 = {0, 0, 0, 0};
+    __device__ inline void mma(double ar, double ai, double br, double bi) {
+        p1 = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, br, p1, 0, 0, 0);
+        if constexpr (is_cplx<T>::value) {
+            p2 = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, bi, p2, 0, 0, 0);
+            p3 = __builtin_amdgcn_mfma_f64_16x16x4f64(ar + ai, br + bi, p3, 0, 0, 0);
+        }
     }
-}
+    __device__ inline double re(int r) const { return is_cplx<T>::value ? p1[r] - p2[r] : p1[r]; }
+    __device__ inline double im(int r) const { return p3[r] - p1[r] - p2[r]; }
+};
 
 template <typename T, int NBS>
 __global__ __launch_bounds__(512) void back_chase_kernel(int n, int b, int nsw, int nblk, const T* V2, const T* Tg,
@@ -698,13 +706,13 @@ __global__ __launch_bounds__(512) void back_chase_kernel(int n, int b, int nsw, 
                     br[kk] = zr[0][(base + r) & (RING - 1)][li];
                     bi[kk] = CX ? zr[NC - 1][(base + r) & (RING - 1)][li] : 0.0;
                 }
-                dbl4 cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
+                BlockAcc<T> acc;
 #pragma unroll
-                for (int kk = 0; kk < KA; ++kk) mma4<T>(cr, ci, ar[kk], ai[kk], br[kk], bi[kk]);
+                for (int kk = 0; kk < KA; ++kk) acc.mma(ar[kk], ai[kk], br[kk], bi[kk]);
 #pragma unroll
                 for (int rr = 0; rr < 4; ++rr) {
-                    wp[0][part][jb * 16 + 4 * rr + lk][li] = cr[rr];
-                    if (CX) wp[NC - 1][part][jb * 16 + 4 * rr + lk][li] = ci[rr];
+                    wp[0][part][jb * 16 + 4 * rr + lk][li] = acc.re(rr);
+                    if (CX) wp[NC - 1][part][jb * 16 + 4 * rr + lk][li] = acc.im(rr);
                 }
             }
             __syncthreads();
@@ -728,13 +736,13 @@ __global__ __launch_bounds__(512) void back_chase_kernel(int n, int b, int nsw, 
                     br[kk] = on ? sr : 0.0;
                     bi[kk] = on ? si : 0.0;
                 }
-                dbl4 cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
+                BlockAcc<T> acc;
 #pragma unroll
-                for (int kk = 0; kk < KP; ++kk) mma4<T>(cr, ci, ar[kk], ai[kk], br[kk], bi[kk]);
+                for (int kk = 0; kk < KP; ++kk) acc.mma(ar[kk], ai[kk], br[kk], bi[kk]);
 #pragma unroll
                 for (int rr = 0; rr < 4; ++rr) {
-                    w1[0][part][jb * 16 + 4 * rr + lk][li] = cr[rr];
-                    if (CX) w1[NC - 1][part][jb * 16 + 4 * rr + lk][li] = ci[rr];
+                    w1[0][part][jb * 16 + 4 * rr + lk][li] = acc.re(rr);
+                    if (CX) w1[NC - 1][part][jb * 16 + 4 * rr + lk][li] = acc.im(rr);
                 }
             }
             __syncthreads();
@@ -750,15 +758,15 @@ __global__ __launch_bounds__(512) void back_chase_kernel(int n, int b, int nsw, 
                     br[ks] = w1[0][0][j][li] + w1[0][1][j][li];
                     bi[ks] = CX ? w1[NC - 1][0][j][li] + w1[NC - 1][1][j][li] : 0.0;
                 }
-                dbl4 cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
+                BlockAcc<T> acc;
 #pragma unroll
-                for (int ks = 0; ks < KS; ++ks) mma4<T>(cr, ci, ar[ks], ai[ks], br[ks], bi[ks]);
+                for (int ks = 0; ks < KS; ++ks) acc.mma(ar[ks], ai[ks], br[ks], bi[ks]);
 #pragma unroll
                 for (int rr = 0; rr < 4; ++rr) {
                     const int rw = wv * 16 + 4 * rr + lk;
                     if (rw < lg) {
-                        zr[0][(base + rw) & (RING - 1)][li] -= cr[rr];
-                        if (CX) zr[NC - 1][(base + rw) & (RING - 1)][li] -= ci[rr];
+                        zr[0][(base + rw) & (RING - 1)][li] -= acc.re(rr);
+                        if (CX) zr[NC - 1][(base + rw) & (RING - 1)][li] -= acc.im(rr);
                     }
                 }
             }
