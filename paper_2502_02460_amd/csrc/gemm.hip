@@ -16,8 +16,12 @@
 // (double-buffered, one barrier per slab).  The MFMA is issued as D = op(B)^T op(A)^T so that
 // 16 lanes of a register hold 16 consecutive rows of one column of C: every
 // store instruction writes 128-byte column segments of the column-major C.
-// Complex products use four real MFMAs per complex k-step (re*re - im*im,
-// re*im + im*re) on separately staged real/imaginary tiles.
+// Complex products run on separately staged real/imaginary tiles.  The
+// eight-wave tiles with 32 x 32 wave blocks use three real MFMAs per
+// complex k-step (Gauss: P1 = re*re, P2 = im*im, P3 = (re + im)(re + im);
+// real part P1 - P2, imaginary part P3 - P1 - P2, formed once in the
+// epilogue), 3/4 of the four-product form's matrix-core work; other tiles
+// and the FP32 compute type use four (re*re - im*im, re*im + im*re).
 //
 // Reduced-precision form: inside a Fp32Gemm scope the operands are rounded
 // to FP32 when staged into LDS and the products run on the FP32 matrix
@@ -165,13 +169,18 @@ __global__ __launch_bounds__(WAVE * WGM * WGN) void gemm_kernel(GemmP<T> p) {
     const int lane = t % WAVE, w = t / WAVE;
     const int wm = w % WGM, wn = w / WGM;
 
-    AccT accR[FA][FB], accI[FA][FB];
+    // three-product complex form for the FP64 compute type, on the
+    // eight-wave tiles whose 32 x 32 wave blocks leave room for the third
+    // accumulator set (elsewhere it would cost occupancy or spill)
+    constexpr bool G3 = CX && std::is_same<CT, double>::value && WGM * WGN == 8 && FA * FB <= 4;
+    AccT accR[FA][FB], accI[FA][FB], accX[FA][FB];
 #pragma unroll
     for (int a = 0; a < FA; ++a)
 #pragma unroll
         for (int b = 0; b < FB; ++b) {
             accR[a][b] = AccT{0, 0, 0, 0};
             accI[a][b] = AccT{0, 0, 0, 0};
+            accX[a][b] = AccT{0, 0, 0, 0};
         }
 
     // The next operand slab is loaded into registers while the MFMAs read the
@@ -244,7 +253,24 @@ __global__ __launch_bounds__(WAVE * WGM * WGN) void gemm_kernel(GemmP<T> p) {
 #pragma unroll
                 for (int qb = 0; qb < FB; ++qb)
                     accR[qa][qb] = Acc<CT>::mma(bR[qb], aR[qa], accR[qa][qb]);
-            if (CX) {
+            if constexpr (G3) {
+                // accR = P1 (above), accI = P2, accX = P3
+#pragma unroll
+                for (int qa = 0; qa < FA; ++qa)
+#pragma unroll
+                    for (int qb = 0; qb < FB; ++qb)
+                        accI[qa][qb] = Acc<CT>::mma(bI[qb], aI[qa], accI[qa][qb]);
+                CT aS[FA], bS[FB];
+#pragma unroll
+                for (int q = 0; q < FA; ++q) aS[q] = aR[q] + aI[q];
+#pragma unroll
+                for (int q = 0; q < FB; ++q) bS[q] = bR[q] + bI[q];
+#pragma unroll
+                for (int qa = 0; qa < FA; ++qa)
+#pragma unroll
+                    for (int qb = 0; qb < FB; ++qb)
+                        accX[qa][qb] = Acc<CT>::mma(bS[qb], aS[qa], accX[qa][qb]);
+            } else if (CX) {
 #pragma unroll
                 for (int qa = 0; qa < FA; ++qa)
 #pragma unroll
@@ -302,7 +328,10 @@ __global__ __launch_bounds__(WAVE * WGM * WGN) void gemm_kernel(GemmP<T> p) {
                     if (col < 0) continue;
                 }
                 T v;
-                if constexpr (CX) v = zdouble{(double)accR[qa][qb][r], (double)accI[qa][qb][r]};
+                if constexpr (G3)
+                    v = zdouble{accR[qa][qb][r] - accI[qa][qb][r],
+                                accX[qa][qb][r] - accR[qa][qb][r] - accI[qa][qb][r]};
+                else if constexpr (CX) v = zdouble{(double)accR[qa][qb][r], (double)accI[qa][qb][r]};
                 else v = (double)accR[qa][qb][r];
                 if (p.splitk > 1) {
                     p.work[(size_t)blockIdx.z * p.m * p.n + IDX(row, col, p.m)] = v;
@@ -367,11 +396,13 @@ constexpr int NTILE = 9;
 constexpr int TILE_BM[NTILE] = {64, 128, 64, 128, 64, 32, 128, 128, 64};
 constexpr int TILE_BN[NTILE] = {64, 64, 128, 128, 32, 64, 128, 64, 128};
 int g_tile_override = -2;  // -2: not read yet, -1: none
-// Measured on gfx950 (FP64, n = 16384 class shapes): the eight-wave
-// 128 x 128 tile runs square products about 20 % faster than 64 x 64 (real
-// and complex) and rank-2k updates as fast or faster; 128 x 64 and 64 x 128
-// win for outputs 64 wide.  They need enough tiles to fill the 256 CUs (one
-// such workgroup per CU), so medium products keep 64 x 64.
+// Measured on gfx950 (FP64, n = 16384 class shapes).  Complex: the
+// eight-wave 64 x 128 tile with the three-product form runs square products
+// at 60-66 TFLOP/s against 45-49 for 64 x 64, rank-2k updates at 43 against
+// 38, and 128 x 64 wins for outputs 64 wide.  Real: the eight-wave
+// 128 x 128 tile runs square products about 20 % faster than 64 x 64.  The
+// eight-wave tiles need enough tiles to fill the 256 CUs (one such
+// workgroup per CU), so medium products keep 64 x 64.
 int pick_tile(int m, int n, bool cx, int splitk, int batch, int tmode) {
     if (g_tile_override == -2) {
         const char* e = getenv("GEVD_GEMM_TILE");
@@ -383,6 +414,11 @@ int pick_tile(int m, int n, bool cx, int splitk, int batch, int tmode) {
     const long long par = (long long)splitk * batch;
     const long long tm = (m + 127) / 128, tn = (n + 127) / 128;
     const bool tri = tmode != T_ALL;
+    if (cx) {
+        if (n <= 64 && m > 64) return tm * par >= 256 ? 7 : 0;
+        if (m <= 64) return tn * par >= 256 ? 8 : 0;
+        return ((m + 63) / 64) * tn * par / (tri ? 2 : 1) >= 512 ? 8 : 0;
+    }
     if (m > 64 && n > 64 && tm * tn * par / (tri ? 2 : 1) >= 512) return 6;
     if (m <= 64 && n > 64 && tn * par >= 256) return 8;
     if (n <= 64 && m > 64 && tm * par >= 256) return 7;
