@@ -31,6 +31,7 @@ from __future__ import annotations
 import heapq
 import math
 import queue
+import sys
 import threading
 import time
 from dataclasses import dataclass, field
@@ -131,7 +132,7 @@ class Scheduler:
 
     def __init__(self, budget_bytes: int, large_workers: int, small_workers: int, small_n: int,
                  workspace_of, executor, batch_executor=None, batch: int = 8, batch_wait: float = 0.02,
-                 clock=time.perf_counter):
+                 clock=time.perf_counter, progress=None):
         self.budget = budget_bytes
         self.workspace_of = workspace_of
         self.executor = executor
@@ -145,6 +146,7 @@ class Scheduler:
         self.cv = threading.Condition(self.lock)
         self.in_use = 0
         self.result = StreamResult()
+        self.progress = progress  # called as progress(done, total, seconds) after each finished request
 
     def _cls(self, req: Request) -> str:
         return "small" if req.n <= self.small_n else "large"
@@ -168,7 +170,10 @@ class Scheduler:
                 self.in_use -= cost
                 self.free[cls] += 1
                 done_count[0] += n_req
+                done = done_count[0]
                 self.cv.notify_all()
+            if self.progress is not None:
+                self.progress(done, outstanding, self.clock() - t0)
 
         def launch(cls: str, batch_reqs: list[Request]):
             cost = sum(footprint_bytes(r, self.workspace_of(r)) for r in batch_reqs)
@@ -399,7 +404,7 @@ def batched_scf(solver, reqs: list[Request], t0: float, on_solve=None, keep: boo
 
 def serve(requests: list[Request], device=None, budget_bytes: int | None = None, large_workers: int = 2,
           small_workers: int = 2, small_n: int = 512, batch: int = 8, batch_wait: float = 0.02,
-          keep_results: bool = False) -> StreamResult:
+          keep_results: bool = False, progress=None) -> StreamResult:
     """Serve a request stream on one GPU; returns per-solve records."""
     import torch
 
@@ -416,7 +421,7 @@ def serve(requests: list[Request], device=None, budget_bytes: int | None = None,
         return gevd.workspace_bytes(torch.complex128 if r.cplx else torch.float64, r.n, r.k)
 
     sched = Scheduler(budget_bytes, large_workers, small_workers, small_n, workspace_of, workers.run_request,
-                      workers.run_batch, batch=batch, batch_wait=batch_wait)
+                      workers.run_batch, batch=batch, batch_wait=batch_wait, progress=progress)
     res = sched.run(requests)
     res.results = workers.results
     return res
@@ -533,7 +538,10 @@ def main():
         print(json.dumps(batched_throughput(args.requests, args.iters, tune=args.tune)), flush=True)
         return
     reqs = poisson_stream(args.requests, args.rate, large=(1024, args.large_max), iters=args.iters)
-    res = serve(reqs, large_workers=args.large_workers, small_workers=args.small_workers)
+    def progress(done, total, secs):
+        print("served %d/%d requests at %.1f s" % (done, total, secs), file=sys.stderr, flush=True)
+
+    res = serve(reqs, large_workers=args.large_workers, small_workers=args.small_workers, progress=progress)
     out = res.summary()
     out.update({"requests": args.requests, "rate_per_s": args.rate, "iters": args.iters,
                 "error_messages": [m for _, m in res.errors][:4]})
