@@ -59,6 +59,13 @@ extern "C" {
 #define GEVD_OPT_KSTATS 4   /* 1: time kernel families with HIP events (see gevd_get_kernel_stats) */
 #define GEVD_OPT_PRECISION 5 /* GEVD_PREC_FP64 (default) or GEVD_PREC_FP32_REFINE */
 #define GEVD_OPT_REFINE 6   /* refinement sweeps of the reduced-precision form (0..10, default 2) */
+/* GEVD_OPT_PANEL: 1 (default) factors each full -> band panel in one
+ * persistent launch whose workgroups (at most 64, one CU each) must all be
+ * resident at once; meant for a device the solve has to itself.  0 uses one
+ * launch per panel column, which needs no co-residency: use it when several
+ * solves share the device (concurrent persistent panels can otherwise wait
+ * for each other's CUs until the wait bound, GEVD_E_HANG).  0 or 1. */
+#define GEVD_OPT_PANEL 7
 
 /* Precision forms (GEVD_OPT_PRECISION) of gevd_solve, gevd_solve_resident
  * and gevd_eigh.  FP32_REFINE: the products of the full -> band reduction

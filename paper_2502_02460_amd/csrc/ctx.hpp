@@ -13,6 +13,7 @@ struct gevd_ctx {
     int timing = 0;
     int prec = 0;          // GEVD_OPT_PRECISION
     int refine_iters = 2;  // GEVD_OPT_REFINE
+    int panel_persist = 1; // GEVD_OPT_PANEL
     char* ws = nullptr;  // workspace (device)
     size_t ws_bytes = 0;
     int* flags = nullptr;  // small device status area

@@ -86,6 +86,7 @@ struct KScope {
 // Its work may not use the last few CUs, which stay free for the latency-
 // bound kernels running on the handle's stream at the same time.
 void attach_aux(gevd_ctx* h, StageCtx& sc) {
+    sc.panel_persist = h->panel_persist;
     if (!h->aux) {
         int ncu = 0;
         if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h->device) != hipSuccess) ncu = 0;
@@ -377,6 +378,10 @@ int gevd_set_option(gevd_handle h, int option, int value) {
         case GEVD_OPT_REFINE:
             if (value < 0 || value > 10) return -3;
             h->refine_iters = value;
+            return 0;
+        case GEVD_OPT_PANEL:
+            if (value != 0 && value != 1) return -3;
+            h->panel_persist = value;
             return 0;
         default:
             return -2;

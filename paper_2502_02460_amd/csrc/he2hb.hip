@@ -475,7 +475,7 @@ int he2hb(const StageCtx& c, int n, T* A, long lda, BandRefl<T>& R, T* Bd, long 
         T* Vp = R.V + R.voff(p);
         T* Tp = R.Tf + (size_t)p * b * b;
         const int gall = (m + PT - 1) / PT;
-        if (gall <= PANEL_MAX_WG && c.hang) {
+        if (gall <= PANEL_MAX_WG && c.hang && c.panel_persist) {
             // one persistent launch for the panel (writes all m x b entries of Vp)
             double fl = 0.0;
             for (int s = 0; s <= nref; ++s) fl += (double)(m - (s > 0 ? s - 1 : 0)) * std::max(0, b - s);

@@ -17,6 +17,9 @@ struct StageCtx {
     // pairs against a copy of A)
     int prec = 0;
     int refine_iters = 2;
+    // 1: one persistent launch per full -> band panel (needs its grid
+    // resident at once); 0: one launch per panel column
+    int panel_persist = 1;
     // optional second stream and two events (owned by the handle): the
     // full -> band reduction runs each trailing update beside the next
     // panel's factorization

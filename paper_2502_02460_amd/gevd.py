@@ -23,7 +23,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 SO_PATH = os.path.join(_HERE, "libgevd.so")
 
 GEVD_REAL, GEVD_COMPLEX = 0, 1
-OPT_BAND, OPT_TIMING, OPT_LEAF, OPT_KSTATS, OPT_PRECISION, OPT_REFINE = 1, 2, 3, 4, 5, 6
+OPT_BAND, OPT_TIMING, OPT_LEAF, OPT_KSTATS, OPT_PRECISION, OPT_REFINE, OPT_PANEL = 1, 2, 3, 4, 5, 6, 7
 PREC_FP64, PREC_FP32_REFINE = 0, 1
 KFAMILIES = ("gemm", "panel", "chase", "backchase", "dc", "other", "small", "gemm32")
 SMALL_MAX = 512
@@ -143,7 +143,10 @@ class Solver:
     calls.  Work goes to the current torch stream of that device."""
 
     def __init__(self, device=None, band: int = 0, leaf: int = 0, timing: bool = False, kstats: bool = False,
-                 precision: str = "fp64", refine: int = 2):
+                 precision: str = "fp64", refine: int = 2, persistent_panel: bool = True):
+        """persistent_panel=False: one launch per full -> band panel column
+        instead of one persistent launch per panel (for several solves
+        sharing the device)."""
         L = load()
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else
                                    torch.device(device).index or 0)
@@ -158,6 +161,8 @@ class Solver:
             _check(L.gevd_set_option(h, OPT_TIMING, 1), "gevd_set_option")
         if kstats:
             _check(L.gevd_set_option(h, OPT_KSTATS, 1), "gevd_set_option")
+        if not persistent_panel:
+            _check(L.gevd_set_option(h, OPT_PANEL, 0), "gevd_set_option")
         self.set_precision(precision, refine)
 
     def set_kstats(self, on: bool):

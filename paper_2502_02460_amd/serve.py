@@ -321,7 +321,8 @@ class GpuWorkers:
 
         if not hasattr(self.local, "solver"):
             self.local.stream = torch.cuda.Stream(device=self.device)
-            self.local.solver = gevd.Solver(self.device)
+            # several solves share the device: panels without co-residency
+            self.local.solver = gevd.Solver(self.device, persistent_panel=False)
         return self.local.solver, self.local.stream
 
     def run_request(self, req: Request, on_solve, t0: float):
@@ -436,7 +437,7 @@ def solve_alone(req: Request, device=None, small_n: int = 512):
     from . import gevd
 
     device = torch.device(device or "cuda:0")
-    solver = gevd.Solver(device)
+    solver = gevd.Solver(device, persistent_panel=False)  # the server's panel route
     if req.n <= small_n:
         outs, _ = batched_scf(solver, [req], 0.0)
         solver.close()

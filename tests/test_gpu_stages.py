@@ -247,3 +247,27 @@ def test_wide_band_tridiagonal_and_solve(gpu_lib, n, b, cplx):
     assert err < 1e-10 and eta < 1e-11
     assert orth < max(1e-11, 10 * orth_ref)
     s.close()
+
+
+# ------------------------------------- per-column panels (GEVD_OPT_PANEL = 0)
+@pytest.mark.parametrize("cplx", [False, True])
+@pytest.mark.parametrize("n", [700, 1100])
+def test_per_column_panel_route(gpu_lib, n, cplx):
+    """The full -> band panels as one launch per column (the route for
+    several solves sharing the device) give a solve of the same quality as
+    the persistent panel kernel."""
+    s = gpu_lib.Solver(persistent_panel=False)
+    p = synth.pencil(n, cplx, 1e-6, 1500 + n, 0.3)
+    w_ref, C_ref, _ = oracle.gevd(p.H, p.S, p.k)
+    ws, C = s.solve(dev(p.H), dev(p.S), p.k)
+    ws, C = host(ws), host(C)
+    err = np.abs(ws - w_ref).max() / np.abs(w_ref).max()
+    eta = backward_errors(p.H, p.S, ws[: p.k], C).max()
+    orth, orth_ref = s_orthonormality(p.S, C), s_orthonormality(p.S, C_ref)
+    log(f"per-column panels n={n} cplx={cplx}: eig {err:.2e} eta {eta:.2e} orth {orth:.2e} (oracle {orth_ref:.2e})")
+    assert err < 1e-10 and eta < 1e-11
+    assert orth < max(1e-11, 10 * orth_ref)
+    L = gpu_lib.load()
+    assert L.gevd_set_option(s._h, gpu_lib.OPT_PANEL, 1) == 0
+    assert L.gevd_set_option(s._h, gpu_lib.OPT_PANEL, 2) == -3
+    s.close()
