@@ -81,6 +81,16 @@ constexpr int WAVE = 64;
 __device__ inline double shfl_xor_s(double v, int m) { return __shfl_xor(v, m, 64); }
 __device__ inline zdouble shfl_xor_s(zdouble v, int m) { return {__shfl_xor(v.x, m, 64), __shfl_xor(v.y, m, 64)}; }
 
+// Value of v in lane `lane` of the wavefront (lane uniform), as a scalar
+// broadcast: two 32-bit lane reads per double.
+__device__ inline double lane_bcast(double v, int lane) {
+    const long long u = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)u, lane);
+    const int hi = __builtin_amdgcn_readlane((int)(u >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ inline zdouble lane_bcast(zdouble v, int lane) { return {lane_bcast(v.x, lane), lane_bcast(v.y, lane)}; }
+
 // Sum over a 64-lane wavefront (all lanes receive the result).
 __device__ inline double wave_sum(double v) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);

@@ -38,6 +38,46 @@ constexpr unsigned long long WAIT_LIMIT_TICKS = 120ull * 100000000ull;
 // cached lines on that XCD).
 __device__ inline int ntasks(int n, int b, int sw) { return (n - 1 - sw + b - 1) / b; }
 
+// Reflector parameters for x = (alpha, x1..): H^H x = beta e1 with beta real,
+// H = I - tau v v^H, v = (1, x1 * scale, ..); a2 = ||x1..||^2.
+template <typename T>
+__device__ inline void householder(T alpha, double a2, T* tau, double* beta, T* scale) {
+    const double ar = realp(alpha), ai = imagp(alpha);
+    if (a2 == 0.0 && ai == 0.0) {
+        *tau = zero_of<T>();
+        *beta = ar;
+        *scale = zero_of<T>();
+        return;
+    }
+    const double nrm = sqrt(ar * ar + ai * ai + a2);
+    const double bt = ar >= 0.0 ? -nrm : nrm;
+    *tau = div_r(from_real<T>(bt) - alpha, bt);
+    *scale = div_s(from_real<T>(1.0), alpha - from_real<T>(bt));
+    *beta = bt;
+}
+
+// Sum over the 64 lanes of each of C values per lane, C a power of two <= 16:
+// exchanges that halve the values at each step (lane bit 2 log2(C)+1 .. 2
+// picks the half), then two plain exchanges; on return v[0] of lane l holds
+// the sum of value (l >> 2) % C.  Fixed order: the same bits on every run.
+template <typename T, int C>
+__device__ inline void lane_fold(T* v, int lane) {
+    if constexpr (C > 1) {
+        constexpr int H = C / 2;
+        const bool up = (lane & (4 * H)) != 0;
+#pragma unroll
+        for (int i = 0; i < H; ++i) {
+            const T keep = up ? v[i + H] : v[i];
+            const T send = up ? v[i] : v[i + H];
+            v[i] = keep + shfl_xor_s(send, 4 * H);
+        }
+        lane_fold<T, H>(v, lane);
+    } else {
+        v[0] += shfl_xor_s(v[0], 1);
+        v[0] += shfl_xor_s(v[0], 2);
+    }
+}
+
 // Householder reflector for x[0..L-1] (LDS, overwritten by v with v[0] = 1):
 // H^H x = beta e1, beta real; sc[] receives {tau, beta, scale}.  One wave.
 template <typename T>
@@ -46,19 +86,12 @@ __device__ inline void reflect1(T* x, int L, T* sc) {
     double a2 = (lane >= 1 && lane < L) ? abs2(x[lane]) : 0.0;
     a2 = wave_sum(a2);
     if (lane == 0) {
-        const T alpha = x[0];
-        const double ar = realp(alpha), ai = imagp(alpha);
-        if (a2 == 0.0 && ai == 0.0) {
-            sc[0] = zero_of<T>();
-            sc[1] = from_real<T>(ar);
-            sc[2] = zero_of<T>();
-        } else {
-            const double nrm = sqrt(ar * ar + ai * ai + a2);
-            const double bt = ar >= 0.0 ? -nrm : nrm;
-            sc[0] = div_r(from_real<T>(bt) - alpha, bt);
-            sc[1] = from_real<T>(bt);
-            sc[2] = div_s(from_real<T>(1.0), alpha - from_real<T>(bt));
-        }
+        T tau, scale;
+        double beta;
+        householder<T>(x[0], a2, &tau, &beta, &scale);
+        sc[0] = tau;
+        sc[1] = from_real<T>(beta);
+        sc[2] = scale;
     }
     __syncthreads();
     if (lane >= 1 && lane < L) x[lane] = x[lane] * sc[2];
@@ -342,34 +375,40 @@ __global__ __launch_bounds__(64 * CW) void hb2st_kernel_wg(int n, int b, T* Bw, 
                 }
                 if (wv == 0) v[lane] = (lane < L) ? te[0] : zero_of<T>();
                 if (L >= 2) {
-#pragma unroll
-                    for (int k = 0; k < KW; ++k)
-                        if (lane < L && wv + CW * k < b) EL_(lane, wv + CW * k) = te[k];
-                    __syncthreads();
-                    reflect1<T>(v, L, sc);
-                    // y_j = v^H E[:, j]: lane = column, rows split over the waves
-                    const int qi = (L + CW - 1) / CW, i0 = wv * qi, i1 = min(L, i0 + qi);
-                    if (lane < b) {
-                        T acc = zero_of<T>();
-                        for (int i = i0; i < i1; ++i) acc += conjg(v[i]) * EL_(i, lane);
-                        part[wv][lane] = acc;
+                    // the next reflector from column 0 (wave 0's first
+                    // register column): norm by a wave sum, alpha by a lane
+                    // broadcast, no LDS round trip
+                    if (wv == 0) {
+                        const T x = (lane < L) ? te[0] : zero_of<T>();
+                        const double a2 = wave_sum((lane >= 1 && lane < L) ? abs2(x) : 0.0);
+                        T tau, scale;
+                        double beta;
+                        householder<T>(lane_bcast(x, 0), a2, &tau, &beta, &scale);
+                        v[lane] = (lane == 0) ? from_real<T>(1.0) : (lane < L ? x * scale : zero_of<T>());
+                        if (lane == 0) {
+                            sc[0] = tau;
+                            sc[1] = from_real<T>(beta);
+                            sc[2] = scale;
+                        }
                     }
                     __syncthreads();
-                    if (tid < b) {
-                        T acc = part[0][tid];
+                    // y_j = v^H E[:, j] for this wave's columns, summed over the
+                    // lanes (rows) by halving exchanges; lanes 4k .. 4k+3 end
+                    // with y of column wv + CW k
+                    const T vl = v[lane];
+                    T yv[KW];
 #pragma unroll
-                        for (int w = 1; w < CW; ++w) acc += part[w][tid];
-                        y[tid] = acc;
-                    }
-                    __syncthreads();
-                    const T ctau = conjg(sc[0]);
-                    if (lane < L) {
-                        const T cv = ctau * v[lane];
+                    for (int k = 0; k < KW; ++k) yv[k] = conjg(vl) * te[k];
+                    lane_fold<T, KW>(yv, lane);
+                    const T ctau = conjg(sc[0]), beta = sc[1];
+                    const T cv = ctau * vl;
 #pragma unroll
-                        for (int k = 0; k < KW; ++k) {
-                            const int j = wv + CW * k;
-                            if (j == 0) sys_store(&Bw[IDX(b + lane, pr0, ldw)], (lane == 0) ? sc[1] : zero_of<T>());
-                            else if (j < b) sys_store(&Bw[IDX(b + lane - j, pr0 + j, ldw)], te[k] - cv * y[j]);
+                    for (int k = 0; k < KW; ++k) {
+                        const int j = wv + CW * k;
+                        const T yj = lane_bcast(yv[0], 4 * k);
+                        if (lane < L && j < b) {
+                            if (j == 0) sys_store(&Bw[IDX(b + lane, pr0, ldw)], (lane == 0) ? beta : zero_of<T>());
+                            else sys_store(&Bw[IDX(b + lane - j, pr0 + j, ldw)], te[k] - cv * yj);
                         }
                     }
                 } else {

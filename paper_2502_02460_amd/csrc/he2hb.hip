@@ -175,16 +175,6 @@ __global__ __launch_bounds__(PT) void panel_step(T* P, long lda, int m, int b, i
     if (tid == 0) P[IDX(s, s, lda)] = from_real<T>(bt);
 }
 
-// Value of v in lane `lane` of the wavefront (lane uniform), as a scalar
-// broadcast: two 32-bit lane reads per double.
-__device__ inline double lane_bcast(double v, int lane) {
-    const long long u = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_readlane((int)u, lane);
-    const int hi = __builtin_amdgcn_readlane((int)(u >> 32), lane);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
-}
-__device__ inline zdouble lane_bcast(zdouble v, int lane) { return {lane_bcast(v.x, lane), lane_bcast(v.y, lane)}; }
-
 // The whole panel in one launch, column-parallel: lane j of every wave owns
 // column j of RPW consecutive panel rows and keeps them in registers, so the
 // panel is read and written once and the row sums of a column step are
