@@ -154,10 +154,12 @@ def haar_torch(n: int, gen, cplx: bool, device):
     return q * ph[None, :]
 
 
-def pencil_torch(n: int, cplx: bool, sigma_min: float, seed: int, frac: float, device, commuting: bool = False):
+def pencil_torch(n: int, cplx: bool, sigma_min: float, seed: int, frac: float, device, commuting: bool = False,
+                 spectra: bool = False):
     """Same recipe as ``pencil`` drawn in device memory.  Returns (H, S, k,
     exact) where H and S are column-major views (stride (1, n)) and exact is
-    the sorted lam/sigma for a commuting pencil, else None."""
+    the sorted lam/sigma for a commuting pencil, else None; with spectra=True
+    also the drawn lam and sigma (so ||H||_2 = max |lam|, ||S||_2 = max sigma)."""
     import torch
 
     gen = torch.Generator(device=device)
@@ -182,4 +184,6 @@ def pencil_torch(n: int, cplx: bool, sigma_min: float, seed: int, frac: float, d
     S = build(v, sigma)
     del v
     exact = torch.sort(lam / sigma).values if commuting else None
+    if spectra:
+        return H, S, wanted(n, frac), exact, lam, sigma
     return H, S, wanted(n, frac), exact
