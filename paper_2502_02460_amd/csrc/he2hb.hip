@@ -21,7 +21,6 @@ namespace {
 
 constexpr int PT = 256;    // threads per panel workgroup = rows per workgroup
 constexpr int MAXB = 64;  // largest supported band
-constexpr int GCH = 32;   // partial rows gathered per pass by the last workgroup
 
 template <typename T>
 struct PanelScratch {
@@ -55,124 +54,6 @@ __device__ inline void make_reflector(T alpha, double xn2, T* tau, T* scale, dou
     *tau = div_r(from_real<T>(bt) - alpha, bt);
     *scale = div_s(from_real<T>(1.0), alpha - from_real<T>(bt));
     *beta = bt;
-}
-
-// One launch per panel column s (0 <= s <= nref), rows split across
-// workgroups:
-//  1. if s > 0, apply reflector s-1 to this workgroup's rows of columns
-//     j >= s: P[i, j] -= conj(tau) v_i w_j, with v_i = P[i, s-1] * scale
-//     (v[s-1] = 1), and store v into Vp[:, s-1];
-//  2. if s < nref, partial sums of |P[i, s]|^2 (i > s) and of
-//     y_j = sum_{i > s} conj(P[i, s]) P[i, j] (j > s).  The last workgroup
-//     to finish adds the partials in workgroup order, forms reflector s
-//     (beta, tau, scale = 1/(alpha - beta)) and w_j = v_s^H P[:, j] =
-//     conj(scale) y_j + P[s, j], which needs no second pass over the rows.
-template <typename T>
-__global__ __launch_bounds__(PT) void panel_step(T* P, long lda, int m, int b, int s, int nref, T* Vp,
-                                                 PanelScratch<T>* ps, T* partial) {
-    __shared__ T red[PT / WAVE][MAXB + 1];
-    __shared__ T wsh[MAXB];
-    __shared__ int last;
-    const int tid = threadIdx.x, w = tid / WAVE, l = tid % WAVE;
-    const int r0 = s > 0 ? s - 1 : 0;
-    const int r = r0 + blockIdx.x * PT + tid;
-    const bool inr = r < m;
-    if (s > 0 && tid < b) wsh[tid] = ps->w[tid];
-    // this thread's row of the panel, columns s-1 .. b-1, in registers
-    // (fully unrolled so the loads are independent and indexing is static)
-    T row[MAXB];
-#pragma unroll
-    for (int j = 0; j < MAXB; ++j) {
-        row[j] = zero_of<T>();
-        if (inr && j + 1 >= s && j < b) row[j] = P[IDX(r, j, lda)];
-    }
-    __syncthreads();
-    if (s > 0) {
-        const int sp = s - 1;
-        T v = zero_of<T>();
-#pragma unroll
-        for (int j = 0; j < MAXB; ++j)
-            if (j == sp) v = (r == sp) ? from_real<T>(1.0) : row[j] * ps->scale;
-        if (inr) {
-            Vp[IDX(r, sp, m)] = v;
-            const T ctv = conjg(ps->tau[sp]) * v;
-#pragma unroll
-            for (int j = 0; j < MAXB; ++j)
-                if (j >= s && j < b) {
-                    row[j] -= ctv * wsh[j];
-                    P[IDX(r, j, lda)] = row[j];
-                }
-        }
-        if (blockIdx.x == 0)
-            for (int i = tid; i < sp; i += PT) Vp[IDX(i, sp, m)] = zero_of<T>();
-    }
-    if (s >= nref) return;
-    const bool below = r > s && inr;
-    T x = zero_of<T>();
-#pragma unroll
-    for (int j = 0; j < MAXB; ++j)
-        if (j == s && below) x = row[j];
-    double nx = wave_sum(abs2(x));
-    if (l == 0) red[w][MAXB] = from_real<T>(nx);
-    const T cx = conjg(x);
-#pragma unroll
-    for (int j = 0; j < MAXB; ++j)
-        if (j > s && j < b) {
-            T y = wave_sum(cx * row[j]);
-            if (l == 0) red[w][j] = y;
-        }
-    __syncthreads();
-    T* part = partial + (size_t)blockIdx.x * (MAXB + 1);
-    if ((tid > s && tid < b) || tid == MAXB) {
-        T acc = red[0][tid];
-        for (int q = 1; q < PT / WAVE; ++q) acc += red[q][tid];
-        part[tid] = acc;
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    __syncthreads();
-    if (tid == 0) last = (atomicAdd(&ps->counter, 1u) == gridDim.x - 1);
-    __syncthreads();
-    if (!last) return;
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    // gather the workgroups' partials (chunks of GCH rows) into LDS with
-    // independent loads, then add them in workgroup order (deterministic)
-    __shared__ T fin[2];  // tau, scale
-    __shared__ double bt;
-    __shared__ T gath[GCH][MAXB + 1];
-    __shared__ T acc_lds[MAXB + 1];
-    const int G = gridDim.x;
-    if (tid <= MAXB) acc_lds[tid] = zero_of<T>();
-    for (int g0 = 0; g0 < G; g0 += GCH) {
-        const int rows = min(GCH, G - g0);
-        __syncthreads();
-        for (int e = tid; e < rows * (MAXB + 1); e += PT) {
-            const int g = e / (MAXB + 1), c = e % (MAXB + 1);
-            gath[g][c] = ((c > s && c < b) || c == MAXB) ? partial[(size_t)(g0 + g) * (MAXB + 1) + c] : zero_of<T>();
-        }
-        __syncthreads();
-        if (tid <= MAXB) {
-            T acc = acc_lds[tid];
-            for (int g = 0; g < rows; ++g) acc += gath[g][tid];
-            acc_lds[tid] = acc;
-        }
-    }
-    __syncthreads();
-    if (tid == 0) {
-        T tau, scale;
-        double beta;
-        make_reflector<T>(P[IDX(s, s, lda)], realp(acc_lds[MAXB]), &tau, &scale, &beta);
-        fin[0] = tau;
-        fin[1] = scale;
-        bt = beta;
-        ps->tau[s] = tau;
-        ps->scale = scale;
-        ps->beta = beta;
-        ps->counter = 0;
-    }
-    __syncthreads();
-    if (tid > s && tid < b) ps->w[tid] = conjg(fin[1]) * acc_lds[tid] + P[IDX(s, tid, lda)];
-    __syncthreads();
-    if (tid == 0) P[IDX(s, s, lda)] = from_real<T>(bt);
 }
 
 // The whole panel in one launch, column-parallel: lane j of every wave owns
@@ -334,6 +215,95 @@ __global__ __launch_bounds__(PCT) void panel_cols(T* P, long lda, int m, int b, 
     }
 }
 
+// One launch per panel column s (0 <= s <= nref), for panels whose
+// persistent grid would be too large and for solves that share the device
+// (no co-residency needed).  Same column-parallel layout as panel_cols (lane
+// j of every wave holds column j of RPW rows):
+//  1. if s > 0, apply reflector s-1 to columns j >= s: a -= x_i scale
+//     conj(tau) w_j on the rows below s-1 (x = column s-1), a -= conj(tau)
+//     w_j on row s-1 (v = 1 there); the lane of column s-1 stores V's column;
+//  2. store the updated columns;
+//  3. if s < nref, per-lane sums y_j = sum_{i > s} conj(x_i) a_j[i] (x =
+//     column s, so y_s = ||x||^2), added over the waves; the last workgroup
+//     to finish adds all partials in workgroup order, forms reflector s from
+//     alpha = P[s, s] and y_s, stores tau, scale, beta and w_j = conj(scale)
+//     y_j + P[s, j], and writes beta to P[s, s].
+template <typename T>
+__global__ __launch_bounds__(PCT) void panel_col_step(T* P, long lda, int m, int b, int s, int nref, T* Vp,
+                                                      PanelScratch<T>* ps, T* partial) {
+    __shared__ T ysh[PNW][WAVE];
+    __shared__ int last;
+    const int tid = threadIdx.x, g = tid / WAVE, j = tid % WAVE;
+    const int G = gridDim.x;
+    const int rb = blockIdx.x * PT + g * RPW;
+    const bool col = j < b;
+    T a[RPW];
+#pragma unroll
+    for (int i = 0; i < RPW; ++i) a[i] = (col && rb + i < m) ? P[IDX(rb + i, j, lda)] : zero_of<T>();
+    if (s > 0) {
+        const int sp = s - 1;
+        const T scale = ps->scale;
+        const T c1 = (j > sp && col) ? conjg(ps->tau[sp]) * ps->w[j] : zero_of<T>();
+        const T ck = scale * c1;
+#pragma unroll
+        for (int i = 0; i < RPW; ++i) {
+            const int r = rb + i;
+            const T x = lane_bcast(a[i], sp);
+            if (r > sp) a[i] -= x * ck;
+            else if (r == sp) a[i] -= c1;
+            if (j == sp && r < m)
+                Vp[IDX(r, sp, m)] = r > sp ? x * scale : (r == sp ? from_real<T>(1.0) : zero_of<T>());
+        }
+#pragma unroll
+        for (int i = 0; i < RPW; ++i)
+            if (col && j >= s && rb + i < m) P[IDX(rb + i, j, lda)] = a[i];
+    }
+    if (s >= nref) return;
+    T y0 = zero_of<T>(), y1 = zero_of<T>(), y2 = zero_of<T>(), y3 = zero_of<T>();
+#pragma unroll
+    for (int i = 0; i < RPW; i += 4) {
+        y0 += conjg(rb + i > s ? lane_bcast(a[i], s) : zero_of<T>()) * a[i];
+        y1 += conjg(rb + i + 1 > s ? lane_bcast(a[i + 1], s) : zero_of<T>()) * a[i + 1];
+        y2 += conjg(rb + i + 2 > s ? lane_bcast(a[i + 2], s) : zero_of<T>()) * a[i + 2];
+        y3 += conjg(rb + i + 3 > s ? lane_bcast(a[i + 3], s) : zero_of<T>()) * a[i + 3];
+    }
+    ysh[g][j] = (y0 + y1) + (y2 + y3);
+    __syncthreads();
+    if (g == 0) {
+        T t = ysh[0][j];
+#pragma unroll
+        for (int q = 1; q < PNW; ++q) t += ysh[q][j];
+        partial[(size_t)blockIdx.x * WAVE + j] = t;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // partials and the stored columns
+    __syncthreads();
+    if (tid == 0) last = (atomicAdd(&ps->counter, 1u) == (unsigned)G - 1);
+    __syncthreads();
+    if (!last) return;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    T acc = zero_of<T>();
+    for (int q = g; q < G; q += PNW) acc += partial[(size_t)q * WAVE + j];
+    ysh[g][j] = acc;
+    __syncthreads();
+    T tot = ysh[0][j];
+#pragma unroll
+    for (int q = 1; q < PNW; ++q) tot += ysh[q][j];
+    const T prj = col ? P[IDX(s, j, lda)] : zero_of<T>();
+    T tau, scale;
+    double beta;
+    make_reflector<T>(lane_bcast(prj, s), realp(lane_bcast(tot, s)), &tau, &scale, &beta);
+    if (g == 0) {
+        if (j > s && col) ps->w[j] = conjg(scale) * tot + prj;
+        if (j == 0) {
+            ps->tau[s] = tau;
+            ps->scale = scale;
+            ps->beta = beta;
+            ps->counter = 0;
+            P[IDX(s, s, lda)] = from_real<T>(beta);
+        }
+    }
+}
+
 // T (b x b upper) of Q = H_0 ... H_{b-1} = I - V T V^H from the Gram matrix
 // G = V^H V: T[s, s] = tau_s, T[0:s, s] = -tau_s T[0:s, 0:s] G[0:s, s].  G is
 // staged in LDS; four lanes share each row's dot product (strided quarters
@@ -477,12 +447,11 @@ int he2hb(const StageCtx& c, int n, T* A, long lda, BandRefl<T>& R, T* Bd, long 
         } else {
             if ((rc = set_zero<T>(st, m, b, Vp, m))) return rc;
             for (int s = 0; s <= nref; ++s) {
-                const int r0 = s > 0 ? s - 1 : 0;
-                const unsigned g = (unsigned)((m - r0 + PT - 1) / PT);
                 KProbe probe(st, GEVD_K_PANEL,
-                             (is_cplx<T>::value ? 16.0 : 4.0) * (double)(m - r0) * std::max(0, b - s));
-                hipLaunchKernelGGL(panel_step<T>, dim3(g), dim3(PT), 0, st, P, lda, m, b, s, nref, Vp, w.ps,
-                                   w.partialT);
+                             (is_cplx<T>::value ? 16.0 : 4.0) * (double)(m - (s > 0 ? s - 1 : 0)) *
+                                 std::max(0, b - s));
+                hipLaunchKernelGGL(panel_col_step<T>, dim3(gall), dim3(PCT), 0, st, P, lda, m, b, s, nref, Vp,
+                                   w.ps, w.partialT);
                 GEVD_LAUNCH_CHECK();
             }
         }
