@@ -223,33 +223,51 @@ __global__ void merge_deflate_kernel(const double* e, const MergeDesc* md, int n
     double* z = zsrt + off;
     const double dmax = fmax(fabs(d[0]), fabs(d[K - 1]));
     const double tol = 8.0 * DEPS * fmax(dmax, rho);
+    // The previous kept entry stays in registers (zp, dp); the next entry is
+    // loaded one step ahead.  |t c s| <= tol is evaluated exactly (hypot and
+    // divisions) only when the division-free |t zq zp| <= 2 tol (zp^2 + zq^2)
+    // admits it: beyond that bound the exact test fails too, so the
+    // decisions are those of the exact test alone.
     int prev = -1, nrot = 0;
+    double zp = 0.0, dp = 0.0;
+    double zn = K > 0 ? z[0] : 0.0, dn = K > 0 ? d[0] : 0.0;
     for (int q = 0; q < K; ++q) {
+        double zq = zn, dq = dn;
+        if (q + 1 < K) {
+            zn = z[q + 1];
+            dn = d[q + 1];
+        }
         flag[off + q] = 0;
-        if (rho * fabs(z[q]) <= tol) {
+        if (rho * fabs(zq) <= tol) {
             flag[off + q] = 1;
             continue;
         }
         if (prev >= 0) {
-            const double t = d[q] - d[prev];
-            const double tau = hypot(z[prev], z[q]);
-            const double c = z[q] / tau, s = z[prev] / tau;
-            if (fabs(t * c * s) <= tol) {
-                z[q] = tau;
-                z[prev] = 0.0;
-                const double dp = c * c * d[prev] + s * s * d[q];
-                const double dq = s * s * d[prev] + c * c * d[q];
-                d[prev] = dp;
-                d[q] = dq;
-                rq1[off + nrot] = prev;
-                rq2[off + nrot] = q;
-                rcs[off + nrot] = c;
-                rsn[off + nrot] = s;
-                ++nrot;
-                flag[off + prev] = 1;
+            const double t = dq - dp;
+            if (fabs(t * zq * zp) <= 2.0 * tol * (zp * zp + zq * zq)) {
+                const double tau = hypot(zp, zq);
+                const double c = zq / tau, s = zp / tau;
+                if (fabs(t * c * s) <= tol) {
+                    z[q] = tau;
+                    z[prev] = 0.0;
+                    const double dpn = c * c * dp + s * s * dq;
+                    const double dqn = s * s * dp + c * c * dq;
+                    d[prev] = dpn;
+                    d[q] = dqn;
+                    zq = tau;
+                    dq = dqn;
+                    rq1[off + nrot] = prev;
+                    rq2[off + nrot] = q;
+                    rcs[off + nrot] = c;
+                    rsn[off + nrot] = s;
+                    ++nrot;
+                    flag[off + prev] = 1;
+                }
             }
         }
         prev = q;
+        zp = zq;
+        dp = dq;
     }
     int kn = 0, kd = 0;
     for (int q = 0; q < K; ++q) {
