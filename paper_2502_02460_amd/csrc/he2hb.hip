@@ -362,7 +362,14 @@ struct Carve {
     }
 };
 
-constexpr int SK = 4;  // split of the long inner dimension in panel products
+// Split of the inner dimension (m) of Y = A22 V (m x b output): enough
+// splits for about 512 output-tile workgroups of 128 rows, each split at
+// least 512 rows long.
+constexpr int SKY_MAX = 16;
+int sk_y(int m) {
+    const int tm = (m + 127) / 128;
+    return std::max(1, std::min({SKY_MAX, (512 + tm - 1) / tm, m / 512}));
+}
 // The b x b products over the panel's m rows (V^H V, V^H W) are a single
 // output tile: their inner dimension is split into chunks of about 128 rows
 // so that they fill the device (partials added in a fixed order).
@@ -388,7 +395,7 @@ size_t carve_ws(char* base, int n, int b, He2hbWs<T>* w) {
     const size_t nb = (size_t)n * b;
     He2hbWs<T> t;
     t.Y = c.take<T>(nb);
-    t.skY = c.take<T>(SK * nb);
+    t.skY = c.take<T>(SKY_MAX * nb);
     t.LR = c.take<T>(3 * nb);
     t.G = c.take<T>((size_t)b * b);
     t.M1 = c.take<T>((size_t)b * b);
@@ -476,7 +483,7 @@ int he2hb(const StageCtx& c, int n, T* A, long lda, BandRefl<T>& R, T* Bd, long 
         }
         // A22 is kept only in its lower triangle: Y = A22 V reads it as Hermitian
         if ((rc = gemm<T>(st, OP_N, OP_N, m, b, m, one, A22, lda, Vp, m, zero, w.Y, m, K_A_HERM_LOWER, T_ALL,
-                          Batch(), m >= 2048 ? SK : 1, w.skY)))
+                          Batch(), sk_y(m), w.skY)))
             return rc;
         if ((rc = gemm<T>(st, OP_N, OP_N, m, b, b, one, w.Y, m, Tp, b, zero, Wb, m, K_B_UPPER))) return rc;  // X
         if ((rc = gemm<T>(st, OP_C, OP_N, b, b, m, one, Vp, m, Wb, m, zero, w.M1, b, K_FULL, T_ALL, Batch(),
