@@ -34,7 +34,9 @@ CONFIGS = {
 }
 
 FP64_PEAK_TFLOPS = 78.6  # MI355X dense FP64 matrix peak (datasheet); the FP64 vector peak is the same
-# roofline bound of each kernel family
+# roofline bound of each kernel family: the products (GEMM and the stage-2
+# back-transformation's block products) against the FP64 matrix peak; the
+# panel, bulge-chasing, D&C and small-solve kernels are latency/ALU-bound
 FAMILY_BOUND = {"gemm": "mfma", "gemm32": "mfma", "backchase": "mfma", "panel": "alu", "chase": "alu", "dc": "alu",
                 "other": "alu", "small": "alu"}
 

@@ -120,7 +120,8 @@ def scf_perturbation(H0: np.ndarray, request: int, it: int, base_seed: int = 4) 
     return np.asfortranarray(H0 + 1e-3 * 0.5 * (g + g.conj().T))
 
 
-# The five workload configurations (sizes, types and spectra), seeds 0..4.
+# The benchmark workloads (sizes, types and spectra), seeds 0..3: real n = 256
+# (all pairs), real n = 4096 and 8192 (lowest 30 %), complex n = 16384 (lowest 25 %).
 CONFIGS = {
     "c0": dict(n=256, cplx=False, sigma_min=1e-3, frac=1.0, seed=0),
     "c1": dict(n=4096, cplx=False, sigma_min=1e-6, frac=0.30, seed=1),
