@@ -111,3 +111,25 @@ def test_worker_failures_are_reported():
     assert res.summary()["errors"] == len(bad)
     ok = [r for r in reqs if r.rid not in bad]
     assert len(res.records) == sum(r.iters for r in ok)
+
+
+def test_progress_reports_every_finished_request():
+    reqs = serve.poisson_stream(20, 400.0, seed=9, large=(600, 900), iters=2)
+    run_request, run_batch = fake_device()
+    seen = []
+    lock = threading.Lock()
+
+    def progress(done, total, secs):
+        with lock:
+            seen.append((done, total, secs))
+
+    sched = serve.Scheduler(1 << 40, large_workers=2, small_workers=1, small_n=512, workspace_of=lambda r: 0,
+                            executor=run_request, batch_executor=run_batch, batch=4, batch_wait=0.01,
+                            progress=progress)
+    res = sched.run(reqs)
+    assert len(res.records) == sum(r.iters for r in reqs)
+    assert seen and all(t == len(reqs) for _, t, _ in seen)
+    counts = sorted(d for d, _, _ in seen)
+    assert counts[-1] == len(reqs)  # the last report covers every request
+    assert all(b > a for a, b in zip(counts, counts[1:]))  # one report per finished launch
+    assert all(s >= 0.0 for _, _, s in seen)
