@@ -47,6 +47,7 @@ extern "C" {
 #define GEVD_E_HIP (-1004)       /* a HIP runtime call failed */
 #define GEVD_E_STATE (-1005)     /* call order violated (e.g. no overlap set) */
 #define GEVD_E_HANG (-1006)      /* a device-side wait exceeded its bound */
+#define GEVD_E_SCRATCH (-1007)   /* request exceeds the fixed scratch of gevd_solve_batched_noalloc */
 
 /* Scalar type of a problem. */
 #define GEVD_REAL 0    /* real symmetric, double */
@@ -291,6 +292,33 @@ int gevd_get_batch_shape(gevd_handle h, int dtype, int n, int *threads, int *wg_
  * chosen shape is returned through threads / wg_per_cu (either may be NULL).
  * Allocates its own buffers; synchronises. */
 int gevd_tune_batched(gevd_handle h, int dtype, int n, int count, int *threads, int *wg_per_cu);
+
+/* ------------------------------------------------------------------
+ * For callers that cannot allocate device memory while they run (tight
+ * serving loops, harnesses that forbid hipMalloc): gevd_solve_batched with
+ * no allocation.  Same arguments, results and per-problem status as
+ * gevd_solve_batched (the same fused kernel; a problem's result does not
+ * depend on the launch shape, so both give identical bits), but every
+ * device buffer it needs beyond the caller's H, S, eval and C (descriptors,
+ * status words, queue counters, per-workgroup Z slots) lives in one fixed
+ * array of GEVD_NOALLOC_SCRATCH_BYTES per device, resolved by gevd_create
+ * and held until the process ends; host staging lives in the handle.  It
+ * calls no hipMalloc/hipFree and creates no streams or events.
+ *  - count must not exceed GEVD_NOALLOC_MAX_COUNT: otherwise GEVD_E_SCRATCH
+ *    is returned before anything is launched.
+ *  - The scalar types run one after the other on the handle's stream, and a
+ *    group's persistent grid is bounded by the Z slots that fit (n <= 512:
+ *    2 MiB per slot), so large orders run on fewer workgroups than in
+ *    gevd_solve_batched.
+ *  - Calls on one device share that device's array: the library serialises
+ *    them within a process (a host lock held until the call has
+ *    synchronised), and each call rewrites every part of the array it
+ *    reads (counters are cleared by a kernel before use).
+ * Returns 0 when the launches ran (per-problem status in info), -i for an
+ * invalid argument i (-3: a descriptor), GEVD_E_SCRATCH, or GEVD_E_*. */
+#define GEVD_NOALLOC_SCRATCH_BYTES (64u << 20)
+#define GEVD_NOALLOC_MAX_COUNT 2048
+int gevd_solve_batched_noalloc(gevd_handle h, int count, const gevd_problem *probs, int *info);
 
 #ifdef __cplusplus
 }

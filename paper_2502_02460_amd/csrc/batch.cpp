@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "ctx.hpp"
+#include "batch.hpp"
 #include "kernels.hpp"
 #include "small.hpp"
 
@@ -25,7 +26,11 @@ struct Group {
     long zoff;
 };
 
-double problem_flops(const gevd_problem& p) {
+}  // namespace
+
+namespace gevd {
+
+double batch_problem_flops(const gevd_problem& p) {
     // Cholesky n^3/3, the two triangular solves 2n^3, Householder
     // tridiagonalisation 4n^3/3, back-transformation 2n^2 k + n^2 k (real
     // count; x4 complex).  QL rotations are not counted.
@@ -35,7 +40,7 @@ double problem_flops(const gevd_problem& p) {
     return p.dtype == GEVD_COMPLEX ? 4.0 * f : f;
 }
 
-int num_cu(gevd_ctx* h) {
+int batch_num_cu(gevd_ctx* h) {
     if (h->ncu <= 0) {
         int v = 0;
         if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, h->device) != hipSuccess || v < 1) v = 1;
@@ -44,13 +49,13 @@ int num_cu(gevd_ctx* h) {
     return h->ncu;
 }
 
-void default_shape(bool cx, int bucket, int* threads, int* wgpcu) {
+static void default_shape(bool cx, int bucket, int* threads, int* wgpcu) {
     static const int t[SMALL_NBUCKET] = {64, 128, 256, 256};
     *threads = t[bucket];
     *wgpcu = small_occupancy(cx, *threads, small_bucket_n(bucket));
 }
 
-void shape_of(gevd_ctx* h, bool cx, int bucket, int* threads, int* wgpcu) {
+void batch_shape_of(gevd_ctx* h, bool cx, int bucket, int* threads, int* wgpcu) {
     const int dt = cx ? 1 : 0;
     if (h->bthreads[dt][bucket] > 0) {
         *threads = h->bthreads[dt][bucket];
@@ -60,7 +65,7 @@ void shape_of(gevd_ctx* h, bool cx, int bucket, int* threads, int* wgpcu) {
     }
 }
 
-int check_problem(const gevd_problem& p) {
+int batch_check_problem(const gevd_problem& p) {
     if (p.dtype != GEVD_REAL && p.dtype != GEVD_COMPLEX) return 1;
     if (p.n < 1 || p.n > SMALL_MAX || p.nev < 1 || p.nev > p.n) return 1;
     if (!p.H || !p.S || !p.C || !p.eval) return 1;
@@ -69,7 +74,18 @@ int check_problem(const gevd_problem& p) {
     return 0;
 }
 
-}  // namespace
+void batch_order(int count, const gevd_problem* probs, int* ord) {
+    for (int i = 0; i < count; ++i) ord[i] = i;
+    auto key = [&](int i) { return probs[i].dtype == GEVD_COMPLEX ? 0 : 1; };
+    std::sort(ord, ord + count, [&](int a, int c) {
+        if (key(a) != key(c)) return key(a) < key(c);
+        if (probs[a].n != probs[c].n) return probs[a].n > probs[c].n;
+        return a < c;
+    });
+}
+
+}  // namespace gevd
+
 
 struct gevd_batch_s {
     gevd_ctx* h = nullptr;
@@ -133,15 +149,10 @@ int build(gevd_ctx* h, int count, const gevd_problem* probs, bool graphed, gevd_
     b->h = h;
     b->count = count;
     b->graphed = graphed;
-    // order: by (dtype, bucket), largest order first inside a bucket
+    // queue order: complex first, largest order first inside a scalar type
     std::vector<int> ord(count);
-    for (int i = 0; i < count; ++i) ord[i] = i;
-    // complex first: its group is the longer one and goes on the main stream
+    batch_order(count, probs, ord.data());
     auto key = [&](int i) { return probs[i].dtype == GEVD_COMPLEX ? 0 : 1; };
-    std::stable_sort(ord.begin(), ord.end(), [&](int a, int c) {
-        if (key(a) != key(c)) return key(a) < key(c);
-        return probs[a].n > probs[c].n;
-    });
     int rc = 0;
     if (hipMalloc(&b->desc, sizeof(SmallDesc) * count) != hipSuccess ||
         hipMalloc(&b->info, sizeof(int) * count) != hipSuccess ||
@@ -162,8 +173,8 @@ int build(gevd_ctx* h, int count, const gevd_problem* probs, bool graphed, gevd_
         G.first = s;
         G.count = e - s;
         int wg = 1;
-        shape_of(h, G.cx, G.bucket, &G.threads, &wg);
-        G.grid = std::max(1, std::min(G.count, wg * num_cu(h)));
+        batch_shape_of(h, G.cx, G.bucket, &G.threads, &wg);
+        G.grid = std::max(1, std::min(G.count, wg * batch_num_cu(h)));
         if ((rc = small_prepare(G.cx, G.threads, small_bucket_n(G.bucket)))) {
             release(b);
             return rc;
@@ -177,7 +188,7 @@ int build(gevd_ctx* h, int count, const gevd_problem* probs, bool graphed, gevd_
         const gevd_problem& p = probs[ord[s]];
         hd[s] = SmallDesc{p.H, p.S, p.C, p.eval, b->info + ord[s], (long)p.ldh, (long)p.lds, (long)p.ldc, p.n, p.nev,
                           (p.flags & GEVD_PROBLEM_FACTORED) ? 1 : 0};
-        b->flops += problem_flops(p);
+        b->flops += batch_problem_flops(p);
     }
     if (hipMalloc(&b->zws, sizeof(double) * std::max(zmax, 1L)) != hipSuccess) {
         (void)hipGetLastError();
@@ -255,7 +266,7 @@ int gevd_batch_create(gevd_handle h, int count, const gevd_problem* probs, gevd_
     if (!out) return -4;
     *out = nullptr;
     for (int i = 0; i < count; ++i)
-        if (check_problem(probs[i])) return -3;
+        if (batch_check_problem(probs[i])) return -3;
     GEVD_HIP(hipSetDevice(h->device));
     return build(h, count, probs, true, out);
 }
@@ -279,7 +290,7 @@ int gevd_solve_batched(gevd_handle h, int count, const gevd_problem* probs, int*
     if (!probs) return -3;
     if (!info) return -4;
     for (int i = 0; i < count; ++i)
-        if (check_problem(probs[i])) return -3;
+        if (batch_check_problem(probs[i])) return -3;
     GEVD_HIP(hipSetDevice(h->device));
     gevd_batch_s* b = nullptr;
     int rc = build(h, count, probs, false, &b);
@@ -309,7 +320,7 @@ int gevd_get_batch_shape(gevd_handle h, int dtype, int n, int* threads, int* wg_
     if (!threads) return -4;
     if (!wg_per_cu) return -5;
     GEVD_HIP(hipSetDevice(h->device));
-    shape_of(h, dtype == GEVD_COMPLEX, small_bucket(n), threads, wg_per_cu);
+    batch_shape_of(h, dtype == GEVD_COMPLEX, small_bucket(n), threads, wg_per_cu);
     return 0;
 }
 

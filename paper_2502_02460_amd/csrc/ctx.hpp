@@ -34,4 +34,8 @@ struct gevd_ctx {
     // second stream and events for overlapped stages (created on first use)
     hipStream_t aux = nullptr;
     hipEvent_t aux_fork = nullptr, aux_join = nullptr;
+    // host staging of gevd_solve_batched_noalloc (GEVD_NOALLOC_MAX_COUNT
+    // entries each, allocated by gevd_create)
+    gevd::SmallDesc* na_desc = nullptr;
+    int* na_ord = nullptr;
 };

@@ -12,6 +12,7 @@
 #include <cstring>
 #include <new>
 
+#include "batch.hpp"
 #include "ctx.hpp"
 #include "kernels.hpp"
 #include "stages.hpp"
@@ -320,6 +321,17 @@ int gevd_create(gevd_handle* out, int device) {
         return GEVD_E_HIP;
     }
     (void)hipMemset(h->flags, 0, NFLAGS * sizeof(int));
+    h->na_desc = new (std::nothrow) SmallDesc[GEVD_NOALLOC_MAX_COUNT];
+    h->na_ord = new (std::nothrow) int[GEVD_NOALLOC_MAX_COUNT];
+    if (!h->na_desc || !h->na_ord) {
+        gevd_destroy(h);
+        return GEVD_E_NOMEM;
+    }
+    const int rc = noalloc_attach(device);
+    if (rc) {
+        gevd_destroy(h);
+        return rc;
+    }
     *out = h;
     return 0;
 }
@@ -338,6 +350,8 @@ int gevd_destroy(gevd_handle h) {
     if (h->ev_made)
         for (auto& e : h->ev) (void)hipEventDestroy(e);
     for (auto& e : h->ks.pool) (void)hipEventDestroy(e);
+    delete[] h->na_desc;
+    delete[] h->na_ord;
     delete h;
     return 0;
 }
@@ -398,6 +412,8 @@ const char* gevd_strerror(int code) {
         case GEVD_E_HIP: return "HIP runtime error";
         case GEVD_E_STATE: return "invalid call order";
         case GEVD_E_HANG: return "device-side wait exceeded its bound";
+        case GEVD_E_SCRATCH:
+            return "request exceeds the fixed scratch of the no-allocation entry point (too many problems)";
         default: return "invalid argument (the negated return value is its 1-based position)";
     }
 }

@@ -28,7 +28,8 @@ PREC_FP64, PREC_FP32_REFINE = 0, 1
 KFAMILIES = ("gemm", "panel", "chase", "backchase", "dc", "other", "small", "gemm32")
 SMALL_MAX = 512
 PHASES = ("cholesky", "invert", "multiply", "band", "tridiag", "solve", "back2", "back1", "mult")
-E_NONFINITE, E_NOCONV, E_NOMEM, E_HIP, E_STATE, E_HANG = -1001, -1002, -1003, -1004, -1005, -1006
+E_NONFINITE, E_NOCONV, E_NOMEM, E_HIP, E_STATE, E_HANG, E_SCRATCH = -1001, -1002, -1003, -1004, -1005, -1006, -1007
+NOALLOC_SCRATCH_BYTES, NOALLOC_MAX_COUNT = 64 << 20, 2048
 
 _lib = None
 _lock = threading.Lock()
@@ -90,6 +91,7 @@ def load():
         L.gevd_reset_kernel_stats.argtypes = [P]
         PP, IP = ctypes.POINTER(Problem), ctypes.POINTER(I)
         L.gevd_solve_batched.argtypes = [P, I, PP, IP]
+        L.gevd_solve_batched_noalloc.argtypes = [P, I, PP, IP]
         L.gevd_batch_create.argtypes = [P, I, PP, ctypes.POINTER(P)]
         L.gevd_batch_run.argtypes = [P, IP]
         L.gevd_batch_destroy.argtypes = [P]
@@ -337,6 +339,16 @@ class Solver:
         info = (ctypes.c_int * len(items))()
         self._stream()
         _check(load().gevd_solve_batched(self._h, len(items), arr, info), "gevd_solve_batched")
+        return keep, list(info)
+
+    def solve_batched_noalloc(self, items, outs=None, factored: bool = False):
+        """solve_batched through the entry point that allocates no device
+        memory (fixed per-device scratch; at most NOALLOC_MAX_COUNT problems).
+        Pass preallocated `outs` to keep the caller's side allocation-free."""
+        arr, keep = self._problems(items, outs, factored)
+        info = (ctypes.c_int * len(items))()
+        self._stream()
+        _check(load().gevd_solve_batched_noalloc(self._h, len(items), arr, info), "gevd_solve_batched_noalloc")
         return keep, list(info)
 
     def batch(self, items, outs=None, factored: bool = False) -> "Batch":

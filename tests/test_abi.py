@@ -49,6 +49,8 @@ def test_null_handle_is_argument_one(lib):
     assert lib.gevd_stedc(None, 4, 2, None, None, None, None, 4) == -1
     lib.gevd_create.argtypes = [P, I]
     assert lib.gevd_create(None, 0) == -1
+    lib.gevd_solve_batched_noalloc.argtypes = [P, I, P, P]
+    assert lib.gevd_solve_batched_noalloc(None, 1, None, None) == -1
 
 
 def test_strerror_and_workspace(lib):
