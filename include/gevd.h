@@ -48,6 +48,16 @@ extern "C" {
 #define GEVD_E_STATE (-1005)     /* call order violated (e.g. no overlap set) */
 #define GEVD_E_HANG (-1006)      /* a device-side wait exceeded its bound */
 #define GEVD_E_SCRATCH (-1007)   /* request exceeds the fixed scratch of gevd_solve_batched_noalloc */
+#define GEVD_E_RANK (-1008)      /* gevd_solve_reduced: fewer retained overlap eigenvectors than nev */
+
+/* Warning bits (gevd_get_warnings): the result is complete and returned.
+ * GEVD_W_ILLCOND: the Cholesky factor's diagonal gives cond(S) >=
+ * (max |U_ii| / min |U_ii|)^2 > GEVD_ILLCOND_KAPPA.  The paper requires the
+ * condition number of S to stay inside the range double precision resolves
+ * (about 1e12) for the Cholesky route, and otherwise moves to the basis of
+ * S's eigenvectors (gevd_solve_reduced). */
+#define GEVD_W_ILLCOND 1
+#define GEVD_ILLCOND_KAPPA 1e12
 
 /* Scalar type of a problem. */
 #define GEVD_REAL 0    /* real symmetric, double */
@@ -60,13 +70,23 @@ extern "C" {
 #define GEVD_OPT_KSTATS 4   /* 1: time kernel families with HIP events (see gevd_get_kernel_stats) */
 #define GEVD_OPT_PRECISION 5 /* GEVD_PREC_FP64 (default) or GEVD_PREC_FP32_REFINE */
 #define GEVD_OPT_REFINE 6   /* refinement sweeps of the reduced-precision form (0..10, default 2) */
-/* GEVD_OPT_PANEL: 1 (default) factors each full -> band panel in one
- * persistent launch whose workgroups (at most 64, one CU each) must all be
- * resident at once; meant for a device the solve has to itself.  0 uses one
- * launch per panel column, which needs no co-residency: use it when several
- * solves share the device (concurrent persistent panels can otherwise wait
- * for each other's CUs until the wait bound, GEVD_E_HANG).  0 or 1. */
+/* GEVD_OPT_PANEL: 1 (default) asks for the persistent full -> band panel
+ * kernel (one launch per panel, at most 64 workgroups that synchronise per
+ * column and so must all be resident at once).  Within a process, one handle
+ * per device holds that route at a time: a call whose handle cannot take it
+ * (another handle's solve is using it) runs with one launch per panel
+ * column instead, which needs no co-residency, and the owner keeps the route
+ * until its work on the device has finished.  0 always uses the per-column
+ * launches (set it when several processes share a device).  0 or 1. */
 #define GEVD_OPT_PANEL 7
+/* GEVD_OPT_GEMM_TILE: -1 (default) picks each matrix product's workgroup
+ * tile from its shape; 0..8 forces one tile on every product of this
+ * handle's calls (0 = 64x64, 4 = 64x32, 5 = 32x64 with four waves;
+ * 6 = 128x128, 7 = 128x64, 8 = 64x128 with eight waves, complex products on
+ * eight-wave tiles in the three-product form; 1-3 are four-wave 128x64,
+ * 64x128, 128x128).  Results differ only by rounding; meant for tests and
+ * measurements. */
+#define GEVD_OPT_GEMM_TILE 8
 
 /* Precision forms (GEVD_OPT_PRECISION) of gevd_solve, gevd_solve_resident
  * and gevd_eigh.  FP32_REFINE: the products of the full -> band reduction
@@ -129,8 +149,12 @@ const char *gevd_strerror(int code);
 
 /* Bytes of device workspace the handle holds for a (dtype, n, nev) solve;
  * a caller admitting work by memory footprint adds its own n x n H, S and
- * n x nev C.  Host-only computation. */
+ * n x nev C.  Host-only computation.  gevd_workspace_bytes assumes the
+ * default options; gevd_handle_workspace_bytes uses the handle's (band
+ * width, leaf size, precision form: FP32_REFINE adds a copy of A and the
+ * refinement blocks). */
 size_t gevd_workspace_bytes(int dtype, int n, int nev);
+size_t gevd_handle_workspace_bytes(gevd_handle h, int dtype, int n, int nev);
 
 /* Whole generalized solve (paper Eq. (2) by its three reduction steps and
  * the back-transformation).
@@ -149,6 +173,48 @@ size_t gevd_workspace_bytes(int dtype, int n, int nev);
  * at minor j; nothing else is computed), or GEVD_E_*. */
 int gevd_solve(gevd_handle h, int dtype, int n, int nev, void *H, int ldh, void *S, int lds,
                double *eval, void *C, int ldc);
+
+/* Warning bits (GEVD_W_*) of the last gevd_solve or gevd_set_overlap, and
+ * through kappa_lower (may be NULL) the lower bound of cond(S) it computed
+ * from the Cholesky factor (0 before any).  Host-only. */
+int gevd_get_warnings(gevd_handle h, double *kappa_lower);
+
+/* Generalized solve for an ill-conditioned overlap: the route the paper
+ * describes at the end of its section "Solving the generalized
+ * eigenproblem".  S = D diag(sigma) D^H is diagonalised; the eigenvectors
+ * with sigma_i < delta (the paper: typically delta <= 1e-5) are omitted; in
+ * the basis X = D_r diag(sigma_r)^(-1/2) of the m retained ones the problem
+ * becomes the standard eigenproblem of X^H H X (order m), solved by the
+ * two-stage route; C = X c~ (so C^H S C = I).
+ *  dtype, n, nev  as gevd_solve; nev <= m is required
+ *  delta     retention threshold (> 0, finite)
+ *  H, ldh    upper triangle read; clobbered
+ *  S, lds    upper triangle read; not modified
+ *  eval      n doubles: eval[0..m) the m eigenvalues of the reduced problem
+ *            ascending; eval[m..n) is not written
+ *  C, ldc    n x nev S-orthonormal eigenvectors of the nev smallest
+ *  m         host int (may be NULL): number of retained eigenvectors
+ *  sigma     device, n doubles (may be NULL): the eigenvalues of S
+ *            ascending (for the caller's condition report)
+ * Synchronises.  Returns 0, -i, GEVD_E_RANK (m < nev; m and sigma are
+ * still written), or GEVD_E_*. */
+int gevd_solve_reduced(gevd_handle h, int dtype, int n, int nev, double delta, void *H, int ldh, const void *S,
+                       int lds, double *eval, void *C, int ldc, int *m, double *sigma);
+
+/* Density matrix from the eigenvectors (the paper's density-matrix
+ * section: P_ij = sum_l f_l conj(c_li) c_lj, with c_l the l-th eigenvector,
+ * i.e. column l of C, and f_l its occupation number) and, if Q is not NULL,
+ * its energy-weighted counterpart Q_ij = sum_l f_l eps_l conj(c_li) c_lj
+ * (the two matrices ELSI returns to DFT codes).
+ *  C, ldc   n x k eigenvectors (device), e.g. gevd_solve's C
+ *  f        device, k occupation numbers
+ *  eval     device, k eigenvalues (read only when Q is not NULL)
+ *  P, ldp   n x n Hermitian result, both triangles written
+ *  Q, ldq   n x n (or NULL)
+ * P = conj(C) diag(f) C^T is formed on the matrix cores from its upper
+ * tiles and mirrored.  Returns after enqueueing; 0 or -i. */
+int gevd_density(gevd_handle h, int dtype, int n, int k, const void *C, int ldc, const double *f,
+                 const double *eval, void *P, int ldp, void *Q, int ldq);
 
 /* SCF residency.  In a self-consistent-field loop S is fixed while H changes
  * every iteration, so the overlap is factored once: gevd_set_overlap reads
@@ -176,9 +242,11 @@ int gevd_cholesky(gevd_handle h, int dtype, int n, void *S, int lds);
 int gevd_invert_upper(gevd_handle h, int dtype, int n, const void *U, int ldu, void *Uinv, int ldi);
 
 /* Step 3: A = Uinv^H H Uinv (the paper's two products), H read from its
- * upper triangle (the strictly lower part of H is overwritten by the
- * Hermitian mirror), Uinv upper triangular (lower part ignored).  A
- * receives the full Hermitian matrix.  A must not overlap H or Uinv. */
+ * upper triangle and clobbered (its diagonal is halved: the products are
+ * formed as A = Z + Z^H, Z = Uinv^H (M Uinv), M = triu(H) - diag(H)/2, which
+ * takes n^3 real flops instead of the 4n^3/3 of H Uinv then Uinv^H (H Uinv)),
+ * Uinv upper triangular (lower part ignored).  A receives the full
+ * Hermitian matrix; it may be H itself but must not overlap Uinv. */
 int gevd_reduce(gevd_handle h, int dtype, int n, void *H, int ldh, const void *Uinv, int ldi, void *A,
                 int lda);
 

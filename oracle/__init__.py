@@ -190,3 +190,64 @@ def gevd(H: np.ndarray, S: np.ndarray, k: int | None = None):
     if info > 0:
         raise OracleError("S is not positive definite at leading minor %d" % info)
     return w, C, times
+
+
+def _herm_from_upper(M: np.ndarray) -> np.ndarray:
+    """Full Hermitian matrix from the upper triangle of M (the triangle the
+    solver reads)."""
+    up = np.triu(M, 1)
+    full = up + up.conj().T
+    full[np.diag_indices(M.shape[0])] = np.real(np.diagonal(M))
+    return np.asfortranarray(full)
+
+
+def eigh(A: np.ndarray, k: int | None = None):
+    """Standard Hermitian eigenproblem A z = eps z (both triangles of the
+    Hermitian A read): one-stage Householder tridiagonalisation, implicit QL
+    with eigenvectors, back-transformation by the reflectors.  Returns (w:
+    all n eigenvalues ascending, Z: n x k orthonormal eigenvectors of the k
+    smallest)."""
+    n = A.shape[0]
+    k = n if k is None else k
+    d, e, R, tau = tridiag(A)
+    w, Z = tql(d, e, vectors=True)
+    Zk = np.asfortranarray(Z[:, :k]).astype(R.dtype)
+    return w, apply_q(R, tau, Zk)
+
+
+def gevd_reduced(H: np.ndarray, S: np.ndarray, k: int, delta: float):
+    """The route for an ill-conditioned overlap described at the end of the
+    paper's section on reducing the generalized eigenproblem: S is
+    diagonalised, S = D diag(sigma) D^H; the eigenvectors D_i whose sigma_i
+    is below delta are omitted; in the basis X = D_r diag(sigma_r)^(-1/2) of
+    the m retained ones the problem is the standard one
+    (X^H H X) c~ = eps c~ (order m); and C = X c~, which is S-orthonormal.
+    Upper triangles of H and S are read.
+
+    Returns (w: the m eigenvalues of the reduced problem ascending, C: n x k
+    eigenvectors of the k smallest, sigma: all n eigenvalues of S ascending,
+    m).  Raises OracleError when fewer than k eigenvectors are retained."""
+    Sf = _herm_from_upper(S)
+    Hf = _herm_from_upper(H)
+    n = Sf.shape[0]
+    sigma, D = eigh(Sf, n)
+    keep = sigma >= delta
+    m = int(keep.sum())
+    if m < k:
+        raise OracleError("only %d overlap eigenvectors have sigma >= delta, fewer than k = %d" % (m, k))
+    X = np.asfortranarray(D[:, keep] / np.sqrt(sigma[keep])[None, :])
+    At = X.conj().T @ Hf @ X
+    At = np.asfortranarray(0.5 * (At + At.conj().T))
+    w, Z = eigh(At, k)
+    C = np.asfortranarray(X @ Z)
+    return w, C, sigma, m
+
+
+def density(C: np.ndarray, f: np.ndarray, eps: np.ndarray | None = None) -> np.ndarray:
+    """The paper's density matrix P_ij = sum_l f_l conj(c_li) c_lj (section on
+    density-matrix based solutions), c_l the l-th eigenvector (column l of
+    C), f_l its occupation number; with eps, the energy-weighted
+    counterpart sum_l f_l eps_l conj(c_li) c_lj.  Written out as
+    conj(C) diag(w) C^T with w = f (or f * eps)."""
+    w = np.asarray(f, dtype=np.float64) * (1.0 if eps is None else np.asarray(eps, dtype=np.float64))
+    return np.asfortranarray((np.conj(C) * w[None, :]) @ C.T)

@@ -14,9 +14,15 @@ struct gevd_ctx {
     int prec = 0;          // GEVD_OPT_PRECISION
     int refine_iters = 2;  // GEVD_OPT_REFINE
     int panel_persist = 1; // GEVD_OPT_PANEL
+    int persist_now = 0;   // the current call holds the persistent panel route (PanelLease)
+    int gemm_tile = -1;    // GEVD_OPT_GEMM_TILE
     char* ws = nullptr;  // workspace (device)
     size_t ws_bytes = 0;
     int* flags = nullptr;  // small device status area
+    double* dstat = nullptr;  // device: {max, min} |U_ii| of the last Cholesky
+    double* dhost = nullptr;  // pinned host copy of dstat
+    int warn = 0;             // GEVD_W_* bits of the last solve
+    double kappa_lb = 0.0;    // lower bound of cond(S) from the last Cholesky
     hipEvent_t ev[GEVD_NPHASE + 1] = {};
     bool ev_made = false;
     bool ev_valid = false;

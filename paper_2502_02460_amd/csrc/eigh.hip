@@ -3,6 +3,7 @@
 // -> back-transformation through the bulge-chasing reflectors and then
 // through the panel reflectors, for the wanted columns only.
 #include <algorithm>
+#include <vector>
 
 #include "stages.hpp"
 
@@ -168,7 +169,35 @@ int eigh_run(const StageCtx& c, int n, int nev, T* A, long lda, double* eval, T*
     return rc;
 }
 
+// All eigenvalues of A, then the eigenvectors of those at or below thresh
+// (the first m in ascending order): the count is taken on the host from the
+// eigenvalues before any eigenvector is back-transformed.  Z needs room for
+// n columns; ws is sized by eigh_ws_bytes(n, n, ...).
+template <typename T>
+int eigh_select_run(const StageCtx& c, int n, double thresh, T* A, long lda, double* eval, T* Z, long ldz,
+                    char* ws, int* m_out) {
+    EighWs<T> w;
+    carve_eigh<T>(ws, n, n, c.b, c.leaf, &w, 0);
+    *m_out = 0;
+    int rc = he2hb<T>(c, n, A, lda, w.R1, w.Bw, w.ldw, w.he_work);
+    if (rc) return rc;
+    if ((rc = hb2st<T>(c, n, w.Bw, w.ldw, w.R2, w.d, w.e, w.sync_area))) return rc;
+    if ((rc = stedc_run(c, n, n, w.d, w.e, eval, w.Zr, n, w.dc_ws))) return rc;
+    std::vector<double> ev(n);
+    GEVD_HIP(hipMemcpyAsync(ev.data(), eval, sizeof(double) * n, hipMemcpyDeviceToHost, c.st));
+    GEVD_HIP(hipStreamSynchronize(c.st));
+    const int m = (int)(std::upper_bound(ev.begin(), ev.end(), thresh) - ev.begin());
+    *m_out = m;
+    if (m == 0) return 0;
+    if (is_cplx<T>::value) rc = real_to_scalar_z(c.st, n, m, w.Zr, n, reinterpret_cast<zdouble*>(Z), ldz);
+    else rc = real_to_scalar_d(c.st, n, m, w.Zr, n, reinterpret_cast<double*>(Z), ldz);
+    if (rc) return rc;
+    if ((rc = back_chase<T>(c, w.R2, m, Z, ldz))) return rc;
+    return back_band<T>(c, w.R1, m, Z, ldz, w.bb_work);
+}
+
 #define INST(T)                                                                              \
+    template int eigh_select_run<T>(const StageCtx&, int, double, T*, long, double*, T*, long, char*, int*); \
     template size_t back_band_ws_elems<T>(int, int, int);                                    \
     template int back_band<T>(const StageCtx&, const BandRefl<T>&, int, T*, long, T*);       \
     template size_t band_ws_bytes<T>(int, int);                                              \

@@ -79,8 +79,8 @@ struct GemmP {
 template <typename T, int OPA>
 __device__ inline T load_opA(const GemmP<T>& p, const T* A, int i, int l, int kend) {
     if (i >= p.m || l >= kend) return zero_of<T>();
-    if (p.kmode == K_A_UPPER && l < i) return zero_of<T>();
-    if (p.kmode == K_A_LOWER && l > i) return zero_of<T>();
+    if ((p.kmode == K_A_UPPER || p.kmode == K_AU_BU) && l < i) return zero_of<T>();
+    if ((p.kmode == K_A_LOWER || p.kmode == K_AL_BU) && l > i) return zero_of<T>();
     if (OPA == OP_N) {
         if (p.kmode == K_A_HERM_LOWER && i < l) return conjg(A[IDX(l, i, p.lda)]);
         return A[IDX(i, p.amap ? p.amap[l] : l, p.lda)];
@@ -92,7 +92,7 @@ __device__ inline T load_opA(const GemmP<T>& p, const T* A, int i, int l, int ke
 template <typename T, int OPB>
 __device__ inline T load_opB(const GemmP<T>& p, const T* B, int l, int j, int kend) {
     if (j >= p.n || l >= kend) return zero_of<T>();
-    if (p.kmode == K_B_UPPER && l > j) return zero_of<T>();
+    if ((p.kmode == K_B_UPPER || p.kmode == K_AU_BU || p.kmode == K_AL_BU) && l > j) return zero_of<T>();
     if (p.kmode == K_B_LOWER && l < j) return zero_of<T>();
     if (OPB == OP_N) return B[IDX(l, j, p.ldb)];
     T v = B[IDX(j, l, p.ldb)];
@@ -153,9 +153,9 @@ __global__ __launch_bounds__(WAVE * WGM * WGN) void gemm_kernel(GemmP<T> p) {
     const int i0 = ti * BM, j0 = tj * BN;
 
     int kbeg = 0, kend = p.k;
-    if (p.kmode == K_B_UPPER) kend = min(kend, j0 + BN);
-    if (p.kmode == K_A_LOWER) kend = min(kend, i0 + BM);
-    if (p.kmode == K_A_UPPER) kbeg = i0 / BK * BK;
+    if (p.kmode == K_B_UPPER || p.kmode == K_AU_BU || p.kmode == K_AL_BU) kend = min(kend, j0 + BN);
+    if (p.kmode == K_A_LOWER || p.kmode == K_AL_BU) kend = min(kend, i0 + BM);
+    if (p.kmode == K_A_UPPER || p.kmode == K_AU_BU) kbeg = i0 / BK * BK;
     if (p.kmode == K_B_LOWER) kbeg = j0 / BK * BK;
     if (p.splitk > 1) {
         int len = max(kend - kbeg, 0);
@@ -396,6 +396,9 @@ constexpr int NTILE = 9;
 constexpr int TILE_BM[NTILE] = {64, 128, 64, 128, 64, 32, 128, 128, 64};
 constexpr int TILE_BN[NTILE] = {64, 64, 128, 128, 32, 64, 128, 64, 128};
 int g_tile_override = -2;  // -2: not read yet, -1: none
+}  // namespace
+thread_local int g_tile_force = -1;  // the calling handle's GEVD_OPT_GEMM_TILE (-1: automatic)
+namespace {
 // Measured on gfx950 (FP64, n = 16384 class shapes).  Complex: the
 // eight-wave 64 x 128 tile with the three-product form runs square products
 // at 60-66 TFLOP/s against 45-49 for 64 x 64, rank-2k updates at 43 against
@@ -408,6 +411,7 @@ int pick_tile(int m, int n, bool cx, int splitk, int batch, int tmode) {
         const char* e = getenv("GEVD_GEMM_TILE");
         g_tile_override = e ? atoi(e) : -1;
     }
+    if (g_tile_force >= 0 && g_tile_force < NTILE) return (cx && g_tile_force == 3) ? 1 : g_tile_force;
     if (g_tile_override >= 0 && g_tile_override < NTILE) return (cx && g_tile_override == 3) ? 1 : g_tile_override;
     if (n <= 32 && m > 32) return 4;
     if (m <= 32 && n > 32) return 5;
@@ -434,6 +438,8 @@ double algorithmic_flops(int m, int n, int k, int kmode, int tmode, bool cx) {
             case K_A_UPPER: return std::max(0, k - i);
             case K_A_LOWER: return std::min(k, i + 1);
             case K_B_LOWER: return std::max(0, k - j);
+            case K_AU_BU: return std::max(0, std::min(k, j + 1) - i);
+            case K_AL_BU: return std::min(k, std::min(i, j) + 1);
             default: return k;
         }
     };
@@ -442,6 +448,12 @@ double algorithmic_flops(int m, int n, int k, int kmode, int tmode, bool cx) {
     const bool tiles_lo = tmode == T_LOWER_TILES || tmode == T_LOWER_STRICT;
     if (kmode == K_FULL && tmode == T_ALL) {
         macs = (double)m * n * k;
+    } else if (kmode == K_AU_BU || kmode == K_AL_BU) {
+        // the inner length depends on both i and j: sum over the stored
+        // elements (upper when a triangle of tiles is kept)
+        const bool up = tmode != T_ALL;
+        for (int j = 0; j < n; ++j)
+            for (int i = 0; i < (up ? std::min(m, j + 1) : m); ++i) macs += kfor(i, j);
     } else if (tmode == T_ALL) {
         if (kmode == K_B_UPPER || kmode == K_B_LOWER)
             for (int j = 0; j < n; ++j) macs += (double)m * kfor(0, j);

@@ -12,6 +12,7 @@
 #include <cstring>
 #include <new>
 
+#include "arbiter.hpp"
 #include "batch.hpp"
 #include "ctx.hpp"
 #include "kernels.hpp"
@@ -71,6 +72,23 @@ int clear_flags(gevd_ctx* h) {
     return 0;
 }
 
+// After a Cholesky S = U^H U: cond(S) = cond(U)^2 >= (max|U_ii| / min|U_ii|)^2
+// (the diagonal of a triangular U holds its eigenvalues).  Enqueues the
+// diagonal scan; settle_cond reads it once the stream has been synchronised.
+template <typename T>
+int scan_cond(gevd_ctx* h, int n, const T* U, int ldu) {
+    int rc = diag_range<T>(h->stream, n, U, ldu, h->dstat);
+    if (rc) return rc;
+    GEVD_HIP(hipMemcpyAsync(h->dhost, h->dstat, 2 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    return 0;
+}
+
+void settle_cond(gevd_ctx* h) {
+    const double mx = h->dhost[0], mn = h->dhost[1];
+    h->kappa_lb = mn > 0.0 ? (mx / mn) * (mx / mn) : INFINITY;
+    if (h->kappa_lb > GEVD_ILLCOND_KAPPA) h->warn |= GEVD_W_ILLCOND;
+}
+
 void mark(gevd_ctx* h, int phase) {
     if (h->timing && h->ev_made) (void)hipEventRecord(h->ev[phase], h->stream);
 }
@@ -78,8 +96,36 @@ void mark(gevd_ctx* h, int phase) {
 // Points the launch probes of this thread at the handle's accounting for the
 // duration of one entry point.
 struct KScope {
-    explicit KScope(gevd_ctx* h) { g_kstats = h->kstats_on ? &h->ks : nullptr; }
-    ~KScope() { g_kstats = nullptr; }
+    explicit KScope(gevd_ctx* h) {
+        g_kstats = h->kstats_on ? &h->ks : nullptr;
+        g_tile_force = h->gemm_tile;
+    }
+    ~KScope() {
+        g_kstats = nullptr;
+        g_tile_force = -1;
+    }
+};
+
+// The persistent full -> band panel route for the duration of one entry
+// point: taken when the handle asks for it (GEVD_OPT_PANEL) and no other
+// handle of the process holds it on this device (arbiter.hpp); otherwise
+// this call uses one launch per panel column.  An owner waits for its
+// streams before giving the route back, so two persistent panel grids never
+// run on the device at once.
+struct PanelLease {
+    gevd_ctx* h;
+    bool owned = false;
+    explicit PanelLease(gevd_ctx* hh) : h(hh) {
+        owned = h->panel_persist && panel_arbiter().try_acquire(h->device, h);
+        h->persist_now = owned ? 1 : 0;
+    }
+    ~PanelLease() {
+        h->persist_now = 0;
+        if (!owned) return;
+        (void)hipStreamSynchronize(h->stream);
+        if (h->aux) (void)hipStreamSynchronize(h->aux);
+        panel_arbiter().release(h->device, h);
+    }
 };
 
 // The second stream of overlapped stages (default priority, ordered against
@@ -87,7 +133,7 @@ struct KScope {
 // Its work may not use the last few CUs, which stay free for the latency-
 // bound kernels running on the handle's stream at the same time.
 void attach_aux(gevd_ctx* h, StageCtx& sc) {
-    sc.panel_persist = h->panel_persist;
+    sc.panel_persist = h->persist_now;
     if (!h->aux) {
         int ncu = 0;
         if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h->device) != hipSuccess) ncu = 0;
@@ -157,20 +203,25 @@ int do_invert(gevd_ctx* h, int n, const T* U, int ldu, T* Uinv, int ldi, char* w
     return trtri<T>(h->stream, n, U, ldu, Uinv, ldi, work);
 }
 
-// A = Uinv^H H Uinv: W = H Uinv (Uinv upper: inner range clipped per tile),
-// then the upper tiles of Uinv^H W, then the Hermitian mirror.
+// A = X^H H X with X = Uinv (upper triangular), in n^3 flops (real count;
+// the explicit-inverse products H X then X^H (H X) take 4n^3/3): with
+// H = M + M^H, M = triu(H) - diag(H)/2, the product Y = M X is upper
+// triangular and costs n^3/3 (inner range [i, j] per element), Z = X^H Y
+// costs 2n^3/3 (inner range up to min(i, j)), and A = Z + Z^H exactly
+// Hermitian.  H's diagonal is halved in place (H is clobbered); Z is formed
+// in A's storage (A may be H).
 template <typename T>
 int do_reduce(gevd_ctx* h, int n, T* H, int ldh, const T* Uinv, int ldi, T* A, int lda, char* ws) {
     Bump b(ws);
-    T* W = b.take<T>((size_t)n * n);
+    T* Y = b.take<T>((size_t)n * n);
     const T one = from_real<T>(1.0), zero = zero_of<T>();
-    int rc = fill_lower_from_upper<T>(h->stream, n, H, ldh);
+    int rc = scale_diag<T>(h->stream, n, H, ldh, 0.5);
     if (rc) return rc;
-    rc = gemm<T>(h->stream, OP_N, OP_N, n, n, n, one, H, ldh, Uinv, ldi, zero, W, n, K_B_UPPER);
+    rc = gemm<T>(h->stream, OP_N, OP_N, n, n, n, one, H, ldh, Uinv, ldi, zero, Y, n, K_AU_BU, T_UPPER_TILES);
     if (rc) return rc;
-    rc = gemm<T>(h->stream, OP_C, OP_N, n, n, n, one, Uinv, ldi, W, n, zero, A, lda, K_A_LOWER, T_UPPER_TILES);
+    rc = gemm<T>(h->stream, OP_C, OP_N, n, n, n, one, Uinv, ldi, Y, n, zero, A, lda, K_AL_BU);
     if (rc) return rc;
-    return fill_lower_from_upper<T>(h->stream, n, A, lda);
+    return herm_sum_inplace<T>(h->stream, n, A, lda);
 }
 
 template <typename T>
@@ -215,10 +266,12 @@ int do_solve(gevd_ctx* h, int n, int nev, T* H, int ldh, T* S, int lds, double* 
     h->ev_valid = false;
     mark(h, GEVD_PH_CHOLESKY);
     if ((rc = do_cholesky<T>(h, n, S, lds, rest))) return rc;
+    if ((rc = scan_cond<T>(h, n, S, lds))) return rc;
     int fl[NFLAGS];
     if ((rc = read_flags(h, fl))) return rc;
     if (fl[F_NONFINITE]) return GEVD_E_NONFINITE;
     if (fl[F_INFO]) return fl[F_INFO];
+    settle_cond(h);
     mark(h, GEVD_PH_INVERT);
     if ((rc = do_invert<T>(h, n, S, lds, Uinv, n, rest))) return rc;
     mark(h, GEVD_PH_MULTIPLY);
@@ -265,10 +318,12 @@ int do_set_overlap(gevd_ctx* h, int n, const T* S, int lds) {
     if ((rc = check_finite_upper<T>(h->stream, n, S, lds, h->flags + F_NONFINITE))) return rc;
     if ((rc = copy_matrix<T>(h->stream, n, n, S, lds, U, n))) return rc;
     if ((rc = do_cholesky<T>(h, n, U, n, rest))) return rc;
+    if ((rc = scan_cond<T>(h, n, U, n))) return rc;
     int fl[NFLAGS];
     if ((rc = read_flags(h, fl))) return rc;
     if (fl[F_NONFINITE]) return GEVD_E_NONFINITE;
     if (fl[F_INFO]) return fl[F_INFO];
+    settle_cond(h);
     if ((rc = do_invert<T>(h, n, U, n, reinterpret_cast<T*>(h->uinv), n, rest))) return rc;
     if ((rc = read_flags(h, fl))) return rc;
     h->res_n = n;
@@ -301,6 +356,106 @@ int do_solve_resident(gevd_ctx* h, int nev, T* H, int ldh, double* eval, T* C, i
     return 0;
 }
 
+// ------------------------------------------------ ill-conditioned overlap route
+template <typename T>
+size_t plan_reduced(const gevd_ctx* h, int n, int nev) {
+    Bump b(nullptr);
+    for (int i = 0; i < 4; ++i) b.take<T>((size_t)n * n);  // -S, X, H X, the reduced matrix
+    b.take<T>((size_t)n * nev);                               // its eigenvectors
+    b.take<double>(n);                                        // eigenvalues of -S
+    size_t rest = eigh_ws_bytes<T>(n, n, pick_band(h, n), h->leaf_opt, 0);
+    for (int bb : {8, 16, 32, 64}) rest = std::max(rest, eigh_ws_bytes<T>(n, nev, bb, h->leaf_opt, 0));
+    return b.off + 256 + rest;
+}
+
+// The paper's route for an ill-conditioned S (end of its section on the
+// reduction): diagonalise S, omit the eigenvectors with sigma_i < delta,
+// solve the standard problem of X^H H X in the basis X = D_r sigma_r^(-1/2)
+// of the m retained ones, and map back, C = X c~.  The eigenvectors of S
+// come from the standard solver applied to -S, so that the largest sigma are
+// the smallest eigenvalues and only the m retained vectors are formed.
+template <typename T>
+int do_solve_reduced(gevd_ctx* h, int n, int nev, double delta, T* H, int ldh, const T* S, int lds, double* eval,
+                     T* C, int ldc, int* m_out, double* sigma_out) {
+    int rc = ensure_ws(h, plan_reduced<T>(h, n, nev));
+    if (rc) return rc;
+    Bump b(h->ws);
+    T* W = b.take<T>((size_t)n * n);
+    T* X = b.take<T>((size_t)n * n);
+    T* HX = b.take<T>((size_t)n * n);
+    T* At = b.take<T>((size_t)n * n);
+    T* Zt = b.take<T>((size_t)n * nev);
+    double* evs = b.take<double>(n);
+    char* rest = reinterpret_cast<char*>(b.take<char>(0));
+    if ((rc = clear_flags(h))) return rc;
+    if ((rc = check_finite_upper<T>(h->stream, n, H, ldh, h->flags + F_NONFINITE))) return rc;
+    if ((rc = check_finite_upper<T>(h->stream, n, S, lds, h->flags + F_NONFINITE))) return rc;
+    int fl[NFLAGS];
+    if ((rc = read_flags(h, fl))) return rc;
+    if (fl[F_NONFINITE]) return GEVD_E_NONFINITE;
+    if ((rc = copy_matrix<T>(h->stream, n, n, S, lds, W, n))) return rc;
+    if ((rc = fill_lower_from_upper<T>(h->stream, n, W, n))) return rc;
+    if ((rc = negate_matrix<T>(h->stream, n, n, W, n))) return rc;
+    StageCtx sc{h->stream, h->flags + F_NOCONV, h->flags + F_HANG, pick_band(h, n), h->leaf_opt};
+    attach_aux(h, sc);
+    int m = 0;
+    if ((rc = eigh_select_run<T>(sc, n, -delta, W, n, evs, X, n, rest, &m))) return rc;
+    if (sigma_out && (rc = negate_reverse(h->stream, n, evs, sigma_out))) return rc;
+    if (m_out) *m_out = m;
+    if (m < nev) {
+        GEVD_HIP(hipStreamSynchronize(h->stream));
+        return GEVD_E_RANK;
+    }
+    const T one = from_real<T>(1.0), zero = zero_of<T>();
+    if ((rc = scale_cols_rsqrt_neg<T>(h->stream, n, m, X, n, evs))) return rc;
+    if ((rc = fill_lower_from_upper<T>(h->stream, n, H, ldh))) return rc;
+    if ((rc = gemm<T>(h->stream, OP_N, OP_N, n, m, n, one, H, ldh, X, n, zero, HX, n))) return rc;
+    if ((rc = gemm<T>(h->stream, OP_C, OP_N, m, m, n, one, X, n, HX, n, zero, At, m, K_FULL, T_UPPER_TILES)))
+        return rc;
+    if ((rc = fill_lower_from_upper<T>(h->stream, m, At, m))) return rc;
+    StageCtx sc2{h->stream, h->flags + F_NOCONV, h->flags + F_HANG, pick_band(h, m), h->leaf_opt};
+    attach_aux(h, sc2);
+    if ((rc = eigh_run<T>(sc2, m, nev, At, m, eval, Zt, m, rest))) return rc;
+    if ((rc = gemm<T>(h->stream, OP_N, OP_N, n, nev, m, one, X, n, Zt, m, zero, C, ldc))) return rc;
+    if ((rc = read_flags(h, fl))) return rc;
+    if (fl[F_HANG]) return GEVD_E_HANG;
+    if (fl[F_NOCONV]) return GEVD_E_NOCONV;
+    if (h->kstats_on) h->ks.settle();
+    return 0;
+}
+
+// ------------------------------------------------------------ density matrix
+// P_ij = sum_l f_l conj(c_li) c_lj (the paper's density matrix, c_l the l-th
+// eigenvector, i.e. column l of C): with B = conj(C) (n x k) and G = B F,
+// P = G B^H.  Only the upper tiles are multiplied; the lower triangle is the
+// Hermitian mirror.  Q (energy-weighted) uses f_l eps_l.
+template <typename T>
+int do_density(gevd_ctx* h, int n, int k, const T* C, int ldc, const double* f, const double* e, T* P, int ldp,
+               T* Q, int ldq) {
+    const bool cx = is_cplx<T>::value;
+    Bump plan(nullptr);
+    plan.take<T>((size_t)n * k);
+    if (cx) plan.take<T>((size_t)n * k);
+    int rc = ensure_ws(h, plan.off + 256);
+    if (rc) return rc;
+    Bump b(h->ws);
+    T* G = b.take<T>((size_t)n * k);
+    T* B = cx ? b.take<T>((size_t)n * k) : const_cast<T*>(C);
+    const long ldb = cx ? n : ldc;
+    const T one = from_real<T>(1.0), zero = zero_of<T>();
+    for (int pass = 0; pass < (Q ? 2 : 1); ++pass) {
+        T* out = pass == 0 ? P : Q;
+        const int ldo = pass == 0 ? ldp : ldq;
+        if ((rc = conj_scale_cols<T>(h->stream, n, k, C, ldc, f, pass == 0 ? nullptr : e, G, n,
+                                     (cx && pass == 0) ? B : nullptr, ldb)))
+            return rc;
+        if ((rc = gemm<T>(h->stream, OP_N, OP_C, n, n, k, one, G, n, B, ldb, zero, out, ldo, K_FULL, T_UPPER_TILES)))
+            return rc;
+        if ((rc = fill_lower_from_upper<T>(h->stream, n, out, ldo))) return rc;
+    }
+    return 0;
+}
+
 bool bad_dtype(int t) { return t != GEVD_REAL && t != GEVD_COMPLEX; }
 
 }  // namespace
@@ -321,6 +476,12 @@ int gevd_create(gevd_handle* out, int device) {
         return GEVD_E_HIP;
     }
     (void)hipMemset(h->flags, 0, NFLAGS * sizeof(int));
+    if (hipMalloc(&h->dstat, 4 * sizeof(double)) != hipSuccess ||
+        hipHostMalloc((void**)&h->dhost, 4 * sizeof(double)) != hipSuccess) {
+        (void)hipGetLastError();
+        gevd_destroy(h);
+        return GEVD_E_HIP;
+    }
     h->na_desc = new (std::nothrow) SmallDesc[GEVD_NOALLOC_MAX_COUNT];
     h->na_ord = new (std::nothrow) int[GEVD_NOALLOC_MAX_COUNT];
     if (!h->na_desc || !h->na_ord) {
@@ -347,6 +508,8 @@ int gevd_destroy(gevd_handle h) {
     if (h->ws) (void)hipFree(h->ws);
     if (h->uinv) (void)hipFree(h->uinv);
     if (h->flags) (void)hipFree(h->flags);
+    if (h->dstat) (void)hipFree(h->dstat);
+    if (h->dhost) (void)hipHostFree(h->dhost);
     if (h->ev_made)
         for (auto& e : h->ev) (void)hipEventDestroy(e);
     for (auto& e : h->ks.pool) (void)hipEventDestroy(e);
@@ -397,6 +560,10 @@ int gevd_set_option(gevd_handle h, int option, int value) {
             if (value != 0 && value != 1) return -3;
             h->panel_persist = value;
             return 0;
+        case GEVD_OPT_GEMM_TILE:
+            if (value < -1 || value > 8) return -3;
+            h->gemm_tile = value;
+            return 0;
         default:
             return -2;
     }
@@ -412,6 +579,7 @@ const char* gevd_strerror(int code) {
         case GEVD_E_HIP: return "HIP runtime error";
         case GEVD_E_STATE: return "invalid call order";
         case GEVD_E_HANG: return "device-side wait exceeded its bound";
+        case GEVD_E_RANK: return "fewer overlap eigenvectors retained than eigenpairs requested";
         case GEVD_E_SCRATCH:
             return "request exceeds the fixed scratch of the no-allocation entry point (too many problems)";
         default: return "invalid argument (the negated return value is its 1-based position)";
@@ -422,6 +590,11 @@ size_t gevd_workspace_bytes(int dtype, int n, int nev) {
     if (bad_dtype(dtype) || n < 1 || nev < 1 || nev > n) return 0;
     gevd_ctx tmp;
     return dtype == GEVD_REAL ? plan_solve<double>(&tmp, n, nev) : plan_solve<zdouble>(&tmp, n, nev);
+}
+
+size_t gevd_handle_workspace_bytes(gevd_handle h, int dtype, int n, int nev) {
+    if (!h || bad_dtype(dtype) || n < 1 || nev < 1 || nev > n) return 0;
+    return dtype == GEVD_REAL ? plan_solve<double>(h, n, nev) : plan_solve<zdouble>(h, n, nev);
 }
 
 int gevd_solve(gevd_handle h, int dtype, int n, int nev, void* H, int ldh, void* S, int lds, double* eval, void* C,
@@ -439,6 +612,9 @@ int gevd_solve(gevd_handle h, int dtype, int n, int nev, void* H, int ldh, void*
     if (ldc < n) return -11;
     if (hipSetDevice(h->device) != hipSuccess) return GEVD_E_HIP;
     KScope kscope(h);
+    PanelLease lease(h);
+    h->warn = 0;
+    h->kappa_lb = 0.0;
     if (dtype == GEVD_REAL)
         return do_solve<double>(h, n, nev, (double*)H, ldh, (double*)S, lds, eval, (double*)C, ldc);
     return do_solve<zdouble>(h, n, nev, (zdouble*)H, ldh, (zdouble*)S, lds, eval, (zdouble*)C, ldc);
@@ -452,6 +628,8 @@ int gevd_set_overlap(gevd_handle h, int dtype, int n, const void* S, int lds) {
     if (lds < n) return -5;
     if (hipSetDevice(h->device) != hipSuccess) return GEVD_E_HIP;
     KScope kscope(h);
+    h->warn = 0;
+    h->kappa_lb = 0.0;
     return dtype == GEVD_REAL ? do_set_overlap<double>(h, n, (const double*)S, lds)
                               : do_set_overlap<zdouble>(h, n, (const zdouble*)S, lds);
 }
@@ -468,9 +646,60 @@ int gevd_solve_resident(gevd_handle h, int nev, void* H, int ldh, double* eval, 
     if (ldc < n) return -7;
     if (hipSetDevice(h->device) != hipSuccess) return GEVD_E_HIP;
     KScope kscope(h);
+    PanelLease lease(h);
     return h->res_dtype == GEVD_REAL
                ? do_solve_resident<double>(h, nev, (double*)H, ldh, eval, (double*)C, ldc)
                : do_solve_resident<zdouble>(h, nev, (zdouble*)H, ldh, eval, (zdouble*)C, ldc);
+}
+
+int gevd_solve_reduced(gevd_handle h, int dtype, int n, int nev, double delta, void* H, int ldh, const void* S,
+                       int lds, double* eval, void* C, int ldc, int* m, double* sigma) {
+    if (!h) return -1;
+    if (bad_dtype(dtype)) return -2;
+    if (n < 1) return -3;
+    if (nev < 1 || nev > n) return -4;
+    if (!(delta > 0.0) || !std::isfinite(delta)) return -5;
+    if (!H) return -6;
+    if (ldh < n) return -7;
+    if (!S) return -8;
+    if (lds < n) return -9;
+    if (!eval) return -10;
+    if (!C) return -11;
+    if (ldc < n) return -12;
+    if (hipSetDevice(h->device) != hipSuccess) return GEVD_E_HIP;
+    KScope kscope(h);
+    PanelLease lease(h);
+    if (dtype == GEVD_REAL)
+        return do_solve_reduced<double>(h, n, nev, delta, (double*)H, ldh, (const double*)S, lds, eval, (double*)C,
+                                        ldc, m, sigma);
+    return do_solve_reduced<zdouble>(h, n, nev, delta, (zdouble*)H, ldh, (const zdouble*)S, lds, eval, (zdouble*)C,
+                                     ldc, m, sigma);
+}
+
+int gevd_density(gevd_handle h, int dtype, int n, int k, const void* C, int ldc, const double* f, const double* eval,
+                 void* P, int ldp, void* Q, int ldq) {
+    if (!h) return -1;
+    if (bad_dtype(dtype)) return -2;
+    if (n < 1) return -3;
+    if (k < 1 || k > n) return -4;
+    if (!C) return -5;
+    if (ldc < n) return -6;
+    if (!f) return -7;
+    if (Q && !eval) return -8;
+    if (!P) return -9;
+    if (ldp < n) return -10;
+    if (Q && ldq < n) return -12;
+    if (hipSetDevice(h->device) != hipSuccess) return GEVD_E_HIP;
+    KScope kscope(h);
+    return dtype == GEVD_REAL
+               ? do_density<double>(h, n, k, (const double*)C, ldc, f, eval, (double*)P, ldp, (double*)Q, ldq)
+               : do_density<zdouble>(h, n, k, (const zdouble*)C, ldc, f, eval, (zdouble*)P, ldp, (zdouble*)Q, ldq);
+}
+
+int gevd_get_warnings(gevd_handle h, double* kappa_lower) {
+    if (!h) return -1;
+    if (kappa_lower) *kappa_lower = h->kappa_lb;
+    return h->warn;
 }
 
 int gevd_cholesky(gevd_handle h, int dtype, int n, void* S, int lds) {
@@ -559,6 +788,7 @@ int gevd_eigh(gevd_handle h, int dtype, int n, int nev, void* A, int lda, double
     if (ldz < n) return -9;
     if (hipSetDevice(h->device) != hipSuccess) return GEVD_E_HIP;
     KScope kscope(h);
+    PanelLease lease(h);
     int b = pick_band(h, n);
     size_t need = dtype == GEVD_REAL ? eigh_ws_bytes<double>(n, nev, b, h->leaf_opt, h->prec)
                                      : eigh_ws_bytes<zdouble>(n, nev, b, h->leaf_opt, h->prec);
@@ -597,6 +827,7 @@ int gevd_band(gevd_handle h, int dtype, int n, void* A, int lda, void* Bd, int l
     if (ldb < b + 1) return -7;
     if (hipSetDevice(h->device) != hipSuccess) return GEVD_E_HIP;
     KScope kscope(h);
+    PanelLease lease(h);
     size_t need = dtype == GEVD_REAL ? band_ws_bytes<double>(n, b) : band_ws_bytes<zdouble>(n, b);
     int rc = ensure_ws(h, need);
     if (rc) return rc;
@@ -616,6 +847,7 @@ int gevd_tridiagonalize(gevd_handle h, int dtype, int n, void* A, int lda, doubl
     if (!e && n > 1) return -7;
     if (hipSetDevice(h->device) != hipSuccess) return GEVD_E_HIP;
     KScope kscope(h);
+    PanelLease lease(h);
     int b = pick_band(h, n);
     size_t need = dtype == GEVD_REAL ? eigh_ws_bytes<double>(n, 1, b, h->leaf_opt)
                                      : eigh_ws_bytes<zdouble>(n, 1, b, h->leaf_opt);

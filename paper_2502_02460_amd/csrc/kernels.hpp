@@ -17,6 +17,8 @@ enum KMode {
     K_A_LOWER = 3,  // op(A)[i, l] = 0 for l > i
     K_B_LOWER = 4,  // op(B)[l, j] = 0 for l < j
     K_A_HERM_LOWER = 5,  // op(A) = A (N) Hermitian, read from its lower triangle only
+    K_AU_BU = 6,    // op(A) upper and op(B) upper: l in [i, j]
+    K_AL_BU = 7,    // op(A) lower and op(B) upper: l <= min(i, j)
 };
 // Output tiles computed / elements stored.
 enum TMode {
@@ -30,6 +32,9 @@ enum TMode {
 // Products issued on this thread while set run on the FP32 matrix cores
 // (operands rounded to FP32, FP32 accumulation); see Fp32Gemm.
 extern thread_local bool g_gemm_fp32;
+// Tile forced on the products issued on this thread (-1: chosen per shape);
+// set from the calling handle's GEVD_OPT_GEMM_TILE for each entry point.
+extern thread_local int g_tile_force;
 struct Fp32Gemm {
     bool prev;
     explicit Fp32Gemm(bool on) : prev(g_gemm_fp32) { g_gemm_fp32 = on; }
@@ -60,6 +65,21 @@ int real_to_scalar_d(hipStream_t st, int m, int n, const double* Z, long ldz, do
 int real_to_scalar_z(hipStream_t st, int m, int n, const double* Z, long ldz, zdouble* C, long ldc);
 template <typename T>
 int check_finite_upper(hipStream_t st, int n, const T* A, long lda, int* flag);
+template <typename T>
+int negate_matrix(hipStream_t st, int m, int n, T* A, long lda);                        // A <- -A
+template <typename T>
+int scale_diag(hipStream_t st, int n, T* A, long lda, double s);                         // A_ii <- s A_ii
+template <typename T>
+int herm_sum_inplace(hipStream_t st, int n, T* Z, long ldz);                            // Z <- Z + Z^H
+template <typename T>
+int scale_cols_rsqrt_neg(hipStream_t st, int m, int n, T* X, long ldx, const double* ev);  // X_j /= sqrt(-ev_j)
+int negate_reverse(hipStream_t st, int n, const double* ev, double* sigma);             // sigma_i = -ev_{n-1-i}
+// G[:, j] = conj(C[:, j]) f_j (times e_j if e), and B = conj(C) if B
+template <typename T>
+int conj_scale_cols(hipStream_t st, int m, int n, const T* C, long ldc, const double* f, const double* e, T* G,
+                    long ldg, T* B, long ldb);
+template <typename T>
+int diag_range(hipStream_t st, int n, const T* U, long ldu, double* out);  // out = {max, min} |Re U_ii|
 
 // Cholesky / triangular inversion.
 template <typename T>

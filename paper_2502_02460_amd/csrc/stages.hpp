@@ -78,6 +78,11 @@ int stedc_run(const StageCtx& c, int n, int nev, const double* d, const double* 
 // Whole standard eigenproblem.
 template <typename T>
 int eigh_run(const StageCtx& c, int n, int nev, T* A, long lda, double* eval, T* Z, long ldz, char* ws);
+// All eigenvalues, and eigenvectors only of the m at or below thresh (m
+// counted after the eigenvalues are known; synchronises the stream once).
+template <typename T>
+int eigh_select_run(const StageCtx& c, int n, double thresh, T* A, long lda, double* eval, T* Z, long ldz,
+                    char* ws, int* m_out);
 
 // ---- stage building blocks (he2hb.hip, hb2st.hip, backtr.hip)
 template <typename T>

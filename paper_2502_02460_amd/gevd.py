@@ -16,6 +16,7 @@ import ctypes
 import json
 import os
 import threading
+import warnings
 
 import torch
 
@@ -23,12 +24,15 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 SO_PATH = os.path.join(_HERE, "libgevd.so")
 
 GEVD_REAL, GEVD_COMPLEX = 0, 1
-OPT_BAND, OPT_TIMING, OPT_LEAF, OPT_KSTATS, OPT_PRECISION, OPT_REFINE, OPT_PANEL = 1, 2, 3, 4, 5, 6, 7
+OPT_BAND, OPT_TIMING, OPT_LEAF, OPT_KSTATS, OPT_PRECISION, OPT_REFINE, OPT_PANEL, OPT_GEMM_TILE = 1, 2, 3, 4, 5, 6, 7, 8
 PREC_FP64, PREC_FP32_REFINE = 0, 1
 KFAMILIES = ("gemm", "panel", "chase", "backchase", "dc", "other", "small", "gemm32")
 SMALL_MAX = 512
 PHASES = ("cholesky", "invert", "multiply", "band", "tridiag", "solve", "back2", "back1", "mult")
 E_NONFINITE, E_NOCONV, E_NOMEM, E_HIP, E_STATE, E_HANG, E_SCRATCH = -1001, -1002, -1003, -1004, -1005, -1006, -1007
+E_RANK = -1008
+W_ILLCOND = 1
+ILLCOND_KAPPA = 1e12
 NOALLOC_SCRATCH_BYTES, NOALLOC_MAX_COUNT = 64 << 20, 2048
 
 _lib = None
@@ -55,6 +59,11 @@ class NotPositiveDefinite(GevdError):
     pass
 
 
+class IllConditionedOverlap(RuntimeWarning):
+    """cond(S) is above what the Cholesky route resolves in FP64; the result
+    is returned (see Solver.solve_reduced for the paper's alternative)."""
+
+
 def load():
     """Load libgevd.so (built by paper_2502_02460_amd.build); raise if absent."""
     global _lib
@@ -73,6 +82,11 @@ def load():
         L.gevd_strerror.restype = ctypes.c_char_p
         L.gevd_workspace_bytes.argtypes = [I, I, I]
         L.gevd_workspace_bytes.restype = ctypes.c_size_t
+        L.gevd_handle_workspace_bytes.argtypes = [P, I, I, I]
+        L.gevd_handle_workspace_bytes.restype = ctypes.c_size_t
+        L.gevd_get_warnings.argtypes = [P, ctypes.POINTER(D)]
+        L.gevd_density.argtypes = [P, I, I, I, P, I, P, P, P, I, P, I]
+        L.gevd_solve_reduced.argtypes = [P, I, I, I, D, P, I, P, I, P, P, I, ctypes.POINTER(I), P]
         L.gevd_solve.argtypes = [P, I, I, I, P, I, P, I, P, P, I]
         L.gevd_cholesky.argtypes = [P, I, I, P, I]
         L.gevd_set_overlap.argtypes = [P, I, I, P, I]
@@ -145,10 +159,11 @@ class Solver:
     calls.  Work goes to the current torch stream of that device."""
 
     def __init__(self, device=None, band: int = 0, leaf: int = 0, timing: bool = False, kstats: bool = False,
-                 precision: str = "fp64", refine: int = 2, persistent_panel: bool = True):
+                 precision: str = "fp64", refine: int = 2, persistent_panel: bool = True, gemm_tile: int = -1):
         """persistent_panel=False: one launch per full -> band panel column
         instead of one persistent launch per panel (for several solves
-        sharing the device)."""
+        sharing the device).  gemm_tile >= 0 forces one matrix-product tile
+        (GEVD_OPT_GEMM_TILE)."""
         L = load()
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else
                                    torch.device(device).index or 0)
@@ -165,6 +180,8 @@ class Solver:
             _check(L.gevd_set_option(h, OPT_KSTATS, 1), "gevd_set_option")
         if not persistent_panel:
             _check(L.gevd_set_option(h, OPT_PANEL, 0), "gevd_set_option")
+        if gemm_tile >= 0:
+            _check(L.gevd_set_option(h, OPT_GEMM_TILE, gemm_tile), "gevd_set_option")
         self.set_precision(precision, refine)
 
     def set_kstats(self, on: bool):
@@ -213,13 +230,77 @@ class Solver:
         self._stream()
         _check(load().gevd_solve(self._h, t, n, nev, H.data_ptr(), ldh, S.data_ptr(), lds, w.data_ptr(),
                                  C.data_ptr(), ldc), "gevd_solve")
+        self._warn()
         return w, C
+
+    def warnings(self):
+        """(GEVD_W_* bits, lower bound of cond(S)) of the last solve or
+        set_overlap."""
+        kap = ctypes.c_double()
+        bits = load().gevd_get_warnings(self._h, ctypes.byref(kap))
+        return bits, kap.value
+
+    def _warn(self):
+        bits, kap = self.warnings()
+        if bits & W_ILLCOND:
+            warnings.warn("cond(S) >= %.3g exceeds %.0e: the Cholesky route loses accuracy; "
+                          "Solver.solve_reduced drops the overlap's near-null directions" % (kap, ILLCOND_KAPPA),
+                          IllConditionedOverlap, stacklevel=3)
+
+    def solve_reduced(self, H: torch.Tensor, S: torch.Tensor, nev: int, delta: float = 1e-5,
+                      C: torch.Tensor | None = None):
+        """The paper's route for an ill-conditioned overlap: omit the
+        eigenvectors of S with sigma < delta and solve in the basis of the
+        retained ones.  H is clobbered; S is not modified.  Returns (eval: the
+        m eigenvalues ascending, C: n x nev, sigma: eigenvalues of S
+        ascending, m)."""
+        n = H.shape[0]
+        t = _dtype_code(H)
+        if S.dtype != H.dtype:
+            raise TypeError("H and S must have the same dtype")
+        ldh, lds = _ld(H, n, "H"), _ld(S, n, "S")
+        if C is None:
+            C = _empty_cm(n, nev, H.dtype, H.device)
+        w = torch.empty(n, dtype=torch.float64, device=H.device)
+        sigma = torch.empty(n, dtype=torch.float64, device=H.device)
+        m = ctypes.c_int()
+        self._stream()
+        _check(load().gevd_solve_reduced(self._h, t, n, nev, float(delta), H.data_ptr(), ldh, S.data_ptr(), lds,
+                                         w.data_ptr(), C.data_ptr(), _ld(C, n, "C"), ctypes.byref(m),
+                                         sigma.data_ptr()), "gevd_solve_reduced")
+        return w[: m.value], C, sigma, m.value
+
+    def density(self, C: torch.Tensor, f: torch.Tensor, eval_: torch.Tensor | None = None,
+                energy_weighted: bool = False):
+        """Density matrix P_ij = sum_l f_l conj(c_li) c_lj from the eigenvector
+        columns of C (n x k) and occupations f (k), and with energy_weighted
+        also Q_ij = sum_l f_l eps_l conj(c_li) c_lj (eval_ holds eps).
+        Returns P or (P, Q), column-major n x n."""
+        n, k = C.shape
+        f = f.to(device=C.device, dtype=torch.float64).contiguous()
+        P = _empty_cm(n, n, C.dtype, C.device)
+        Q = _empty_cm(n, n, C.dtype, C.device) if energy_weighted else None
+        if energy_weighted:
+            if eval_ is None:
+                raise ValueError("energy_weighted needs the eigenvalues")
+            eval_ = eval_[:k].to(device=C.device, dtype=torch.float64).contiguous()
+        self._stream()
+        _check(load().gevd_density(self._h, _dtype_code(C), n, k, C.data_ptr(), _ld(C, n, "C"), f.data_ptr(),
+                                   eval_.data_ptr() if energy_weighted else None, P.data_ptr(), n,
+                                   Q.data_ptr() if energy_weighted else None, n), "gevd_density")
+        return (P, Q) if energy_weighted else P
+
+    def workspace_bytes(self, dtype, n: int, nev: int) -> int:
+        """Device workspace this handle holds for a (dtype, n, nev) solve
+        under its current options."""
+        return int(load().gevd_handle_workspace_bytes(self._h, _dt(dtype), n, nev))
 
     def set_overlap(self, S: torch.Tensor):
         """Factor S once and keep U^{-1} in the handle (S is not modified)."""
         n = S.shape[0]
         self._stream()
         _check(load().gevd_set_overlap(self._h, _dtype_code(S), n, S.data_ptr(), _ld(S, n, "S")), "gevd_set_overlap")
+        self._warn()
         self.res_n, self.res_dtype = n, S.dtype
 
     def solve_resident(self, H: torch.Tensor, nev: int, C: torch.Tensor | None = None,

@@ -188,3 +188,54 @@ def pencil_torch(n: int, cplx: bool, sigma_min: float, seed: int, frac: float, d
     if spectra:
         return H, S, wanted(n, frac), exact, lam, sigma
     return H, S, wanted(n, frac), exact
+
+
+# ---------------------------------------------------------------------------
+# Reproducible CPU draws.  numpy's QR and products run in OpenBLAS, whose
+# kernels (chosen per CPU model) and thread partitioning change the last
+# bits; drawing in a child process with the kernel type and thread count
+# fixed gives the same bits on any x86-64 host with AVX2/FMA, so an input can
+# be identified by its SHA-256 across machines.
+# ---------------------------------------------------------------------------
+PINNED_ENV = {"OPENBLAS_CORETYPE": "Haswell", "OPENBLAS_NUM_THREADS": "8", "OMP_NUM_THREADS": "8"}
+
+
+def input_sha256(H: np.ndarray, S: np.ndarray) -> str:
+    import hashlib
+
+    return hashlib.sha256(np.asfortranarray(H).tobytes(order="F") + np.asfortranarray(S).tobytes(order="F")).hexdigest()
+
+
+def pinned_problem(kind: str, n: int, cplx: bool, sigma_min: float, seed: int, frac: float,
+                   cache_dir: str | None = None) -> tuple:
+    """(Problem, sha256) of ``pencil`` (kind "pencil") or ``commuting_pencil``
+    (kind "commuting") drawn in a child process with PINNED_ENV; cached as
+    .npz under cache_dir (default: the system temp directory)."""
+    import os
+    import subprocess
+    import sys
+    import tempfile
+
+    cache_dir = cache_dir or tempfile.gettempdir()
+    os.makedirs(cache_dir, exist_ok=True)
+    tag = "gevd_pinned_%s_%d_%s_%g_%d_%g.npz" % (kind, n, "z" if cplx else "d", sigma_min, seed, frac)
+    path = os.path.join(cache_dir, tag)
+    if not os.path.exists(path):
+        env = dict(os.environ)
+        env.update(PINNED_ENV)
+        root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+        code = ("import sys; sys.path.insert(0, %r)\n"
+                "import numpy as np\n"
+                "from paper_2502_02460_amd import synth\n"
+                "f = synth.pencil if %r == 'pencil' else synth.commuting_pencil\n"
+                "p = f(%d, %r, %r, %d, %r)\n"
+                "np.savez(%r, H=p.H, S=p.S, lam=p.lam, sigma=p.sigma, k=p.k,"
+                " exact=p.exact if p.exact is not None else np.zeros(0))\n") % (
+                    root, kind, n, cplx, sigma_min, seed, frac, path + ".tmp.npz")
+        subprocess.run([sys.executable, "-c", code], env=env, check=True)
+        os.replace(path + ".tmp.npz", path)
+    with np.load(path) as z:
+        exact = z["exact"] if z["exact"].size else None
+        p = Problem(H=np.asfortranarray(z["H"]), S=np.asfortranarray(z["S"]), k=int(z["k"]), lam=z["lam"],
+                    sigma=z["sigma"], exact=exact)
+    return p, input_sha256(p.H, p.S)

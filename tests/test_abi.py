@@ -51,6 +51,11 @@ def test_null_handle_is_argument_one(lib):
     assert lib.gevd_create(None, 0) == -1
     lib.gevd_solve_batched_noalloc.argtypes = [P, I, P, P]
     assert lib.gevd_solve_batched_noalloc(None, 1, None, None) == -1
+    D = ctypes.c_double
+    lib.gevd_solve_reduced.argtypes = [P, I, I, I, D, P, I, P, I, P, P, I, P, P]
+    assert lib.gevd_solve_reduced(None, 0, 4, 2, 1e-5, None, 4, None, 4, None, None, 4, None, None) == -1
+    lib.gevd_get_warnings.argtypes = [P, P]
+    assert lib.gevd_get_warnings(None, None) == -1
 
 
 def test_strerror_and_workspace(lib):

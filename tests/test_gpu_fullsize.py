@@ -6,28 +6,34 @@ checks are properties that hold at any size:
 
 * a commuting pencil (H and S built on the same Haar eigenvectors) has the
   generalized eigenvalues lam_i / sigma_i exactly, so all n computed
-  eigenvalues are compared with them normwise: the route is normwise
-  backward stable on A = U^-H H U^-1, so each eigenvalue carries an error of
-  order n u ||A|| (||A|| = max |eps|), and the gate is max(1e-10, 256 n u)
-  relative to ||A||;
+  eigenvalues are compared with them normwise: at complex n = 16384 (drawn
+  on the device) against 1e-11 of max |eps|; at real n = 4096 and 8192
+  (drawn on the CPU with pinned BLAS kernels) against max(1e-11, 2x) the
+  oracle's own error on the same input (tests/golden/fullsize_oracle.json),
+  with the backward error over all wanted columns held the same way;
 * for the paper-shaped pencil (independent eigenvectors) and the commuting
   one, sampled eigenpairs are checked by their definitions: backward error
-  ||H c - w S c|| / ((||H|| + |w| ||S||) ||c||) with the 2-norms known from
-  the drawn spectra, and S-orthonormality of the sampled columns.  The
-  backward error of a normwise backward stable route grows like n u; the
-  gate is max(1e-11, 64 n u) (1e-11 up to n ~ 1400; observed at these sizes:
-  6e-13 to 1.2e-11).
+  ||H c - w S c|| / ((||H|| + |w| ||S||) ||c||) <= 1e-11 with the 2-norms
+  known from the drawn spectra, and S-orthonormality of the sampled columns
+  (<= 1e-10).
+
+The real n = 4096 configuration is the exception: the oracle's eigenvalues
+(without eigenvectors) take seconds there, so it is compared with them
+eigenvalue by eigenvalue.
 
 The sampled products run in torch (FP64 library products), not in the
 solver."""
 from __future__ import annotations
 
+import json
+import os
+
 import pytest
 import torch
 
 from paper_2502_02460_amd import synth
+from tests import cases, floors
 from tests.gpu_util import log
-from tests.linalg_checks import U64
 
 pytestmark = pytest.mark.gpu
 
@@ -57,20 +63,64 @@ def _solve(gpu_lib, H0, S0, k):
     return w, C
 
 
-@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
-def test_fullsize_commuting_exact_spectrum(gpu_lib, case):
-    name, n, cplx, frac, smin, seed = case
+def test_fullsize_commuting_exact_spectrum_complex(gpu_lib):
+    """complex n = 16384 (drawn on the device): all n eigenvalues against the
+    exact spectrum (normwise <= 1e-11), sampled backward errors <= 1e-11."""
+    name, n, cplx, frac, smin, seed = CASES[2]
     dev = torch.device("cuda:0")
     H0, S0, k, exact, lam, sigma = synth.pencil_torch(n, cplx, smin, seed, frac, dev, commuting=True,
                                                       spectra=True)
     w, C = _solve(gpu_lib, H0, S0, k)
     err = float((w - exact).abs().max() / exact.abs().max())
     eta, orth = _sampled(H0, S0, w, C, k, float(lam.abs().max()), float(sigma.max()))
-    log(f"full size, commuting pencil, {name}: all {n} eigenvalues vs exact {err:.2e} (normwise); "
-        f"sampled eta {eta:.2e}, S-orthonormality {orth:.2e}")
-    assert err < max(1e-10, 256 * n * U64)
-    assert eta < max(1e-11, 64 * n * U64)
-    assert orth < 1e-9
+    rel = float(((w[:k] - exact[:k]).abs() / exact[:k].abs()).max())
+    log(f"full size, commuting pencil, {name}: all {n} eigenvalues vs exact {err:.2e} (normwise), "
+        f"wanted {rel:.2e} (max relative); sampled eta {eta:.2e}, S-orthonormality {orth:.2e}")
+    assert err < 1e-11
+    assert eta < 1e-11
+    assert orth < 1e-10
+
+
+def _golden_fullsize():
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "fullsize_oracle.json")) as f:
+        return json.load(f)["cases"]
+
+
+@pytest.mark.parametrize("n,seed", [(4096, 31), (8192, 33)])
+def test_fullsize_commuting_real_against_oracle(gpu_lib, n, seed):
+    """real n = 4096 and 8192 commuting pencils drawn on the CPU with pinned
+    BLAS kernels (tests/golden/make_fullsize.py ran the oracle on the same
+    draw, SHA-256 recorded): the GPU's normwise eigenvalue error against the
+    exact spectrum, and its largest backward error over all k wanted
+    columns, within max(1e-11, 2x) the oracle's own on that input; sampled
+    S-orthonormality within max(1e-10, 10x) the oracle's.  At kappa(S) = 1e6
+    the backward error of the Cholesky route is limited by the standard
+    solver's residual relative to ||A|| ~ 5e7, which puts the oracle's own
+    value near 1e-11."""
+    p, sha = synth.pinned_problem("commuting", n, False, 1e-6, seed, 0.3)
+    g = _golden_fullsize()["commuting/n=%d/d/smin=1e-06/seed=%d/f=0.3" % (n, seed)]
+    same = sha == g["sha256"]
+    k = p.k
+    dev = torch.device("cuda:0")
+    H0 = torch.from_numpy(p.H).to(dev)
+    S0 = torch.from_numpy(p.S).to(dev)
+    w, C = _solve(gpu_lib, H0, S0, k)
+    exact = torch.from_numpy(p.exact).to(dev)
+    err = float((w - exact).abs().max() / exact.abs().max())
+    nh, ns = float(abs(p.lam).max()), float(p.sigma.max())
+    R = H0 @ C - (S0 @ C) * w[:k][None, :]
+    eta_all = R.norm(dim=0) / ((nh + w[:k].abs() * ns) * C.norm(dim=0))
+    eta_max = float(eta_all.max())
+    idx = g["sample_index"]
+    Cs = C[:, idx].contiguous()
+    orth = float((Cs.mT @ (S0 @ Cs) - torch.eye(len(idx), dtype=Cs.dtype, device=dev)).abs().max())
+    log(f"full size, commuting pencil, real n={n}: input {'identical to' if same else 'NOT bit-identical to'} "
+        f"the oracle's draw; eigenvalues vs exact {err:.2e} normwise (oracle {g['eig_err_normwise']:.2e}); "
+        f"max eta over all {k} wanted {eta_max:.2e} (oracle {g['eta_max_all']:.2e}); "
+        f"sampled S-orthonormality {orth:.2e} (oracle {g['orth_sampled']:.2e})")
+    assert err <= max(1e-11, 2.0 * g["eig_err_normwise"])
+    assert eta_max <= max(1e-11, 2.0 * g["eta_max_all"])
+    assert orth <= max(1e-10, 10.0 * g["orth_sampled"])
 
 
 @pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
@@ -82,8 +132,31 @@ def test_fullsize_paper_pencil_sampled(gpu_lib, case):
     assert bool((w[1:] >= w[:-1]).all())  # ascending
     eta, orth = _sampled(H0, S0, w, C, k, float(lam.abs().max()), float(sigma.max()))
     log(f"full size, paper-shaped pencil, {name}: sampled eta {eta:.2e}, S-orthonormality {orth:.2e}")
-    assert eta < max(1e-11, 64 * n * U64)
-    assert orth < 1e-9
+    assert eta < 1e-11
+    assert orth < 1e-10
+
+
+def test_fullsize_c1_oracle_parity(gpu_lib):
+    """The real n = 4096 benchmark configuration (lowest 30 %, kappa(S) ~
+    1e6), drawn on the CPU, solved in the launch configuration bench.py times
+    (b = 64, persistent panels, eight-wave tiles where the shapes allow), and
+    compared with the oracle's eigenvalues of the same input (its route
+    without eigenvectors): each wanted eigenvalue within max(1e-12, 10 F) of
+    the oracle's, all n within 1e-11 normwise; sampled backward errors and
+    S-orthonormality of the eigenvectors."""
+    p, key = cases.config_pencil("c1")
+    n, k = p.H.shape[0], p.k
+    w_ref = floors.oracle_eigenvalues(p.H, p.S)
+    dev = torch.device("cuda:0")
+    H0 = torch.from_numpy(p.H).to(dev)
+    S0 = torch.from_numpy(p.S).to(dev)
+    assert H0.stride(0) == 1 and S0.stride(0) == 1  # column-major, as drawn
+    w, C = _solve(gpu_lib, H0, S0, k)
+    floors.check_eigs(w.cpu().numpy(), w_ref, k, floors.stored(key), f"full size c1 n={n} k={k}:")
+    eta, orth = _sampled(H0, S0, w, C, k, float(abs(p.lam).max()), float(p.sigma.max()), count=16)
+    log(f"  sampled eta {eta:.2e}, S-orthonormality {orth:.2e}")
+    assert eta < 1e-11
+    assert orth < 1e-10
 
 
 def test_fullsize_precision_form_error_stated(gpu_lib):
@@ -108,5 +181,5 @@ def test_fullsize_precision_form_error_stated(gpu_lib):
     eta, orth = _sampled(H0, S0, w, C, k, float(lam.abs().max()), float(sigma.max()))
     log(f"full size, precision form, real n={n}: wanted eigenvalues vs exact {err:.2e} normwise "
         f"(FP64 form {err64:.2e}); sampled eta {eta:.2e}, S-orthonormality {orth:.2e}")
-    assert err64 < max(1e-10, 256 * n * U64)
+    assert err64 < 1e-11
     assert err < 1e-6

@@ -2,15 +2,20 @@
 reduction and the stage-1 back-transformation, then FP64 refinement of the
 wanted pairs (Ogita-Aishima correction restricted to their subspace).
 
-What is asserted is what the method can deliver: (1) the FP32 stages alone
-give FP32-level results; (2) when the wanted subspace is well separated
-from the rest of the spectrum, refinement brings the eigenvalues to the
-1e-12 (normwise) level, while the eigenvector residual and S-orthonormality
-stay at the level of the FP32 stages (the subspace correction does not act
-on components outside the computed subspace); (3) for the paper-shaped
-pencils (kappa(S) = 1e6, eigenvalues clustered relative to ||A||) the
-results are reported against the oracle, and refinement must not make them
-worse."""
+The target of this form is the FP64 accuracy: each wanted eigenvalue
+within max(1e-12, 10 F) of the oracle's (F the input's FP64 floor) and
+backward errors <= 1e-11.  test_precision_form_meets_fp64_targets asserts
+exactly that and is marked xfail(strict=True) while the refinement does not
+reach it (measured: see its reason); it turns into a failure the moment it
+passes, so the mark cannot outlive the fix.
+
+The other tests assert what the current form delivers: (1) the FP32 stages
+alone give FP32-level results; (2) when the wanted subspace is well
+separated from the rest of the spectrum, refinement brings the eigenvalues
+to the 1e-11 (normwise) level, while the eigenvector residual and
+S-orthonormality stay at the level of the FP32 stages; (3) for the
+paper-shaped pencils (kappa(S) = 1e6) the results are reported against the
+oracle, and refinement must not make them worse."""
 from __future__ import annotations
 
 import numpy as np
@@ -18,6 +23,7 @@ import pytest
 
 import oracle
 from paper_2502_02460_amd import synth
+from tests import floors
 from tests.gpu_util import dev, host, log
 from tests.linalg_checks import backward_errors, s_orthonormality
 
@@ -84,7 +90,21 @@ def test_paper_shaped_pencil_reported(gpu_lib, n, cplx, smin):
     (ed, hd), (e0, h0), (e2, h2) = out[("fp64", 0)], out[("fp32+refine", 0)], out[("fp32+refine", 2)]
     log(f"paper-shaped n={n} cplx={cplx} sigma_min={smin}: eig fp64 {ed:.2e} fp32 {e0:.2e} refined {e2:.2e}; "
         f"eta fp64 {hd:.2e} fp32 {h0:.2e} refined {h2:.2e}")
-    assert ed < 1e-10
+    assert ed < 1e-11
     assert e0 < 1e-6            # FP32 stages: normwise error at FP32 level
     assert e2 <= 2.0 * e0       # refinement does not make it materially worse
     assert h2 <= 1.1 * h0
+
+
+@pytest.mark.xfail(strict=True, reason="the subspace refinement cannot restore components the FP32 stages lost "
+                                       "outside span(X): measured relative eigenvalue error ~1e-6..1e-4 and eta "
+                                       "~1e-7..3e-4 at kappa(S) = 1e6 against the FP64 targets")
+@pytest.mark.parametrize("n,cplx", [(1024, False), (512, True)])
+def test_precision_form_meets_fp64_targets(gpu_lib, n, cplx):
+    p = synth.pencil(n, cplx, 1e-6, 70 + n, 0.3)
+    w_ref, _, _ = oracle.gevd(p.H, p.S, p.k)
+    w, C = _run(gpu_lib, p.H, p.S, p.k, "fp32+refine", 2)
+    eta = backward_errors(p.H, p.S, w[: p.k], C).max()
+    log(f"precision form n={n} cplx={cplx}: eta {eta:.2e}")
+    floors.check_eigs(w, w_ref, p.k, floors.floor(p.H, p.S, p.k), f"precision form n={n} cplx={cplx}:")
+    assert eta < 1e-11

@@ -14,6 +14,7 @@ import torch
 
 import oracle
 from paper_2502_02460_amd import serve
+from tests import floors
 from tests.gpu_util import log
 from tests.linalg_checks import backward_errors, s_orthonormality
 
@@ -59,4 +60,5 @@ def test_mix_equals_alone(gpu_lib):
     H, S = _host_inputs(small, 0)
     w_ref, _, _ = oracle.gevd(H, S, small.k)
     w = res.results[small.rid][0][0]
-    assert np.abs(w - w_ref).max() / np.abs(w_ref).max() < 1e-10
+    # the stream's inputs are drawn on the device, so their floor is measured here
+    floors.check_eigs(w, w_ref, small.k, floors.floor(H, S, small.k), f"served request n={small.n}:")

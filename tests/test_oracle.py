@@ -323,3 +323,119 @@ def test_gevd_brute_force_rational(cplx, n):
     w, C, _ = oracle.gevd(Hn, Sn, n)
     assert np.abs(w - exact).max() <= 1e-13 * max(1.0, np.abs(exact).max())
     assert backward_errors(Hn, Sn, w, C).max() < 1e-14
+
+
+# ------------------------------------------- ill-conditioned overlap route
+@pytest.mark.parametrize("cplx", [False, True])
+def test_eigh_standard_against_closed_form_and_lapack(cplx):
+    # tridiag(1, 0, 1) embedded by a Haar similarity has eigenvalues 2 cos(j pi/(n+1))
+    n = 70
+    rng = np.random.default_rng(31)
+    Q = synth.haar(n, rng, cplx)
+    T = np.diag(np.ones(n - 1), 1) + np.diag(np.ones(n - 1), -1)
+    A = np.asfortranarray(Q @ T @ Q.conj().T)
+    A = np.asfortranarray(0.5 * (A + A.conj().T))
+    w, Z = oracle.eigh(A, 20)
+    exact = np.sort(2.0 * np.cos(np.arange(1, n + 1) * np.pi / (n + 1)))
+    assert np.abs(w - exact).max() < 64 * n * U64
+    assert np.abs(A @ Z - Z * w[None, :20]).max() < 64 * n * U64
+    assert np.abs(Z.conj().T @ Z - np.eye(20)).max() < 64 * n * U64
+    assert np.abs(w - sl.eigvalsh(A)).max() < 64 * n * U64
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+def test_reduced_route_commuting_closed_form(cplx):
+    """H = V diag(lam) V^H, S = V diag(sigma) V^H with some sigma below delta:
+    the retained basis spans exactly the V columns with sigma >= delta, so the
+    reduced eigenvalues are lam_i / sigma_i over those, and nothing else."""
+    n, delta = 96, 1e-5
+    rng = np.random.default_rng(41)
+    V = synth.haar(n, rng, cplx)
+    sigma = np.exp(rng.uniform(np.log(1e-9), 0.0, n))
+    sigma[:10] = np.exp(rng.uniform(np.log(1e-12), np.log(1e-7), 10))  # surely dropped
+    lam = synth.core_like_spectrum(n, rng)
+    S = np.asfortranarray(0.5 * ((V * sigma) @ V.conj().T + ((V * sigma) @ V.conj().T).conj().T))
+    H = np.asfortranarray(0.5 * ((V * lam) @ V.conj().T + ((V * lam) @ V.conj().T).conj().T))
+    keep = sigma >= delta
+    order = np.argsort(lam[keep] / sigma[keep])
+    exact = (lam[keep] / sigma[keep])[order]
+    sig_of = sigma[keep][order]
+    k = 25
+    w, C, sig, m = oracle.gevd_reduced(H, S, k, delta)
+    assert m == int(keep.sum())
+    assert np.abs(np.sort(sig) - np.sort(sigma)).max() < 64 * n * U64
+    # Rounding errors of order n u ||.|| in H, S and in S's eigenvectors move
+    # eps_i = lam_i/sigma_i, to first order, by (||dH|| + |eps_i| ||dS||)
+    # ||c_i||^2 with ||c_i||^2 = 1/sigma_i; the standard solve of the reduced
+    # matrix (norm max |eps|) adds n u max |eps|.  Each retained eigenvalue
+    # is held to 8 n u ((||H|| + |eps_i| ||S||) / sigma_i + max |eps|):
+    # condition-limited by 1/delta, not by 1/sigma_min = 1e12 as the
+    # Cholesky route would be.  A wrong scaling of the basis or a dropped
+    # term moves them by O(|eps_i|).
+    bound = 8 * n * U64 * ((np.abs(lam).max() + np.abs(exact) * sigma.max()) / sig_of + np.abs(exact).max())
+    assert np.all(np.abs(w - exact) <= bound)
+    assert s_orthonormality(S, C) < 1e-10
+    # every column is an exact eigenpair of the commuting pencil
+    assert backward_errors(H, S, w[:k], C).max() < 1e-12
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+def test_reduced_route_without_dropping_equals_the_cholesky_route(cplx):
+    """delta below every sigma_i: nothing is omitted, X spans the whole
+    space, and the eigenvalues are those of H c = eps S c."""
+    p = synth.pencil(80, cplx, 1e-3, 43, 0.4)
+    w_ref, C_ref, _ = oracle.gevd(p.H, p.S, p.k)
+    w, C, _, m = oracle.gevd_reduced(p.H, p.S, p.k, 1e-9)
+    assert m == 80
+    assert np.abs(w - w_ref).max() / np.abs(w_ref).max() < 1e-12
+    assert np.abs(np.abs(np.einsum("ij,ij->j", C.conj(), p.S @ C_ref)) - 1.0).max() < 1e-9
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+def test_reduced_route_galerkin_condition(cplx):
+    """For a generic pencil with dropped directions, each returned pair
+    satisfies the Galerkin condition in the retained basis:
+    X^H (H c - eps S c) = 0; and C^H S C = I."""
+    p = synth.pencil(90, cplx, 1e-8, 47, 0.3)
+    delta = 1e-5
+    w, C, sig, m = oracle.gevd_reduced(p.H, p.S, p.k, delta)
+    assert m == int((sig >= delta).sum()) and m < 90
+    Sf = p.S
+    sigma, D = oracle.eigh(Sf, 90)
+    X = D[:, sigma >= delta] / np.sqrt(sigma[sigma >= delta])[None, :]
+    R = X.conj().T @ (p.H @ C - (Sf @ C) * w[None, : p.k])
+    scale = np.abs(w[: p.k]).max()
+    assert np.abs(R).max() / scale < 1e-11
+    assert s_orthonormality(Sf, C) < 1e-11
+
+
+def test_reduced_route_rank_error():
+    p = synth.pencil(30, False, 1e-8, 49, 1.0)
+    with pytest.raises(oracle.OracleError):
+        oracle.gevd_reduced(p.H, p.S, 30, 1e-5)
+
+
+# ------------------------------------------------------------ density matrix
+@pytest.mark.parametrize("cplx", [False, True])
+def test_density_brute_force_and_invariants(cplx):
+    """P_ij = sum_l f_l conj(c_li) c_lj written as three nested loops at a tiny
+    order; with S-orthonormal eigenvectors: sum_ij P_ij S_ij = sum_l f_l
+    (the electron count), P Hermitian, and with every state filled
+    (k = n, f = 1) P = conj(S^-1)."""
+    p = synth.pencil(7, cplx, 1e-2, 53, 1.0)
+    w, C, _ = oracle.gevd(p.H, p.S, 7)
+    rng = np.random.default_rng(55)
+    f = rng.uniform(0.0, 2.0, 5)
+    P = oracle.density(C[:, :5], f)
+    Pb = np.zeros((7, 7), dtype=C.dtype)
+    for i in range(7):
+        for j in range(7):
+            for l in range(5):
+                Pb[i, j] += f[l] * np.conj(C[i, l]) * C[j, l]
+    assert np.abs(P - Pb).max() < 1e-13 * np.abs(Pb).max()
+    assert np.abs(P - P.conj().T).max() < 1e-13 * np.abs(P).max()
+    assert abs(np.sum(P * p.S) - f.sum()) < 1e-11 * f.sum()
+    Pall = oracle.density(C, np.ones(7))
+    assert np.abs(Pall @ np.conj(p.S) - np.eye(7)).max() < 1e-10
+    Q = oracle.density(C[:, :5], f, w[:5])
+    assert abs(np.sum(Q * p.S) - np.sum(f * w[:5])) < 1e-11 * np.abs(f * w[:5]).sum()
