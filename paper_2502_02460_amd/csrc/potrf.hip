@@ -1,11 +1,13 @@
 // Step 1 (Cholesky S = U^H U) and step 2 (U -> U^{-1}) of the reduction to
 // standard form (paper, section "Solving the generalized eigenproblem").
 //
-// Cholesky is blocked right-looking over 64-column panels: a one-workgroup
-// kernel factors the 64 x 64 diagonal block in LDS and also inverts it; the
-// row panel U12 = U11^{-H} S12 then is one MFMA product with that inverse
-// (no triangular solve on the critical path), and the trailing update
-// S22 -= U12^H U12 is an MFMA product restricted to upper tiles.
+// Cholesky runs over block rows of 256 rows (left-looking): each block row
+// first receives the contributions of all finished rows as one MFMA product
+// with a long inner dimension, then is factored right-looking in 64-column
+// steps: a one-workgroup kernel factors the 64 x 64 diagonal block in LDS
+// and also inverts it; the rest of its rows U12 = U11^{-H} S12 is one MFMA
+// product with that inverse (no triangular solve on the critical path), and
+// the block row's remaining rows take S22 -= U12^H U12 on upper tiles.
 //
 // The inverse is formed recursively: inv([A B; 0 D]) = [Ai, -Ai B Di; 0, Di],
 // with all 64 x 64 diagonal blocks inverted by one batched launch and every
@@ -137,11 +139,26 @@ int trtri_rec(hipStream_t st, int o, int s, const T* U, long ldu, T* Uinv, long 
                    Uinv + IDX(o, o + s1, ldi), ldi, K_A_UPPER);
 }
 
+// Rows per block row of the Cholesky, and the split of its long inner
+// dimension: a block row is updated by one product with inner length j0
+// (all finished rows above it), split so that the product has enough
+// workgroups to fill the device.
+constexpr int NBR = 256;
+
+int chol_splitk(int jb, int width, int k) {
+    const long tiles = (long)((jb + 63) / 64) * ((width + 127) / 128);
+    int sk = 1;
+    while (sk < 16 && tiles * sk < 512 && k / (2 * sk) >= 256) sk *= 2;
+    return sk;
+}
+
 }  // namespace
 
 template <typename T>
-size_t potrf_work_elems(int) {
-    return (size_t)NB * NB;
+size_t potrf_work_elems(int n) {
+    // the diagonal block's inverse, a 64-row strip for U12, then the
+    // split-K partials of the block-row update (at most 16 splits of NBR x n)
+    return (size_t)NB * NB + 256 + (size_t)NB * std::max(n, 1) + 256 + (size_t)16 * NBR * (size_t)std::max(n, 1);
 }
 template <typename T>
 size_t trtri_work_elems(int n) {
@@ -149,29 +166,53 @@ size_t trtri_work_elems(int n) {
     return h * h;
 }
 
+// Block-row (left-looking) Cholesky.  For each block row of NBR rows:
+//  1. R -= U_above^H U_above_row: all finished rows enter through one MFMA
+//     product whose inner length is the number of finished rows (the long
+//     dimension of the factorisation, so the products run near the matrix
+//     cores' rate instead of as rank-64 updates);
+//  2. the block row is factored right-looking in 64-column steps: the
+//     diagonal 64 x 64 block in LDS (factor and inverse), the rest of its
+//     rows U12 = U11^{-H} R12 by one product with that inverse, and the
+//     remaining rows of the block row updated by U12^H U12 (upper tiles).
 template <typename T>
 int potrf(hipStream_t st, int n, T* S, long lds, T* work, int* info_dev) {
     const T one = from_real<T>(1.0), mone = from_real<T>(-1.0), zero = zero_of<T>();
-    for (int j = 0; j < n; j += NB) {
-        const int jb = min(NB, n - j);
-        {
-            KProbe probe(st, GEVD_K_OTHER, 0.0);
-            hipLaunchKernelGGL(potrf_diag_kernel<T>, dim3(1), dim3(NTD), 0, st, jb, S + IDX(j, j, lds), lds, work,
-                               info_dev, j);
-            GEVD_LAUNCH_CHECK();
+    T* winv = work;
+    T* strip = work + (size_t)NB * NB + 256;
+    T* skw = strip + (size_t)NB * std::max(n, 1) + 256;
+    for (int j0 = 0; j0 < n; j0 += NBR) {
+        const int jb = min(NBR, n - j0);
+        const int width = n - j0;
+        T* R = S + IDX(j0, j0, lds);
+        if (j0 > 0) {
+            const int sk = chol_splitk(jb, width, j0);
+            int rc = gemm<T>(st, OP_C, OP_N, jb, width, j0, mone, S + IDX(0, j0, lds), lds, S + IDX(0, j0, lds), lds,
+                             one, R, lds, K_FULL, T_ALL, Batch(), sk, skw);
+            if (rc) return rc;
         }
-        const int m2 = n - j - jb;
-        if (m2 <= 0) break;
-        T* S12 = S + IDX(j, j + jb, lds);
-        // U12 = inv(U11)^H S12, in place: the product's row count jb <= 64
-        // is a single tile row, so every workgroup reads its whole column
-        // slab of S12 before it writes that slab.
-        int rc = gemm<T>(st, OP_C, OP_N, jb, m2, jb, one, work, NB, S12, lds, zero, S12, lds, K_A_LOWER);
-        if (rc) return rc;
-        // S22 -= U12^H U12 on the upper tiles
-        rc = gemm<T>(st, OP_C, OP_N, m2, m2, jb, mone, S12, lds, S12, lds, one, S + IDX(j + jb, j + jb, lds), lds,
-                     K_FULL, T_UPPER_TILES);
-        if (rc) return rc;
+        for (int s0 = 0; s0 < jb; s0 += NB) {
+            const int sb = min(NB, jb - s0);
+            {
+                KProbe probe(st, GEVD_K_OTHER, 0.0);
+                hipLaunchKernelGGL(potrf_diag_kernel<T>, dim3(1), dim3(NTD), 0, st, sb, R + IDX(s0, s0, lds), lds,
+                                   winv, info_dev, j0 + s0);
+                GEVD_LAUNCH_CHECK();
+            }
+            const int w2 = width - s0 - sb;  // columns right of the diagonal block
+            if (w2 <= 0) break;
+            T* R12 = R + IDX(s0, s0 + sb, lds);
+            // U12 = inv(U11)^H R12 through a strip (whatever the tile height)
+            int rc = gemm<T>(st, OP_C, OP_N, sb, w2, sb, one, winv, NB, R12, lds, zero, strip, NB, K_A_LOWER);
+            if (rc) return rc;
+            if ((rc = copy_matrix<T>(st, sb, w2, strip, NB, R12, lds))) return rc;
+            const int r2 = jb - s0 - sb;  // rows of the block row below this step
+            if (r2 <= 0) continue;
+            // R22 -= U12[:, :r2]^H U12 on the upper tiles of the block row's rest
+            rc = gemm<T>(st, OP_C, OP_N, r2, w2, sb, mone, R12, lds, R12, lds, one, R + IDX(s0 + sb, s0 + sb, lds),
+                         lds, K_FULL, T_UPPER_TILES);
+            if (rc) return rc;
+        }
     }
     return 0;
 }
