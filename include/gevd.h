@@ -87,6 +87,15 @@ extern "C" {
  * 64x128, 128x128).  Results differ only by rounding; meant for tests and
  * measurements. */
 #define GEVD_OPT_GEMM_TILE 8
+/* GEVD_OPT_STAGES: how the standard eigenproblem is tridiagonalised.  2 (and
+ * 0, the default) full -> band -> tridiagonal (two stages, back-transformed
+ * through both); 1 one-stage Householder tridiagonalisation (the route the
+ * paper ran on GPUs for full spectra, section "ELPA - Usability"): every
+ * reflector computed from the panel-corrected column and a memory-bound
+ * product with the trailing matrix, rank-2x32 MFMA updates per panel, and a
+ * single back-transformation.  The one-stage route always runs in FP64 (the
+ * precision form applies to the two-stage route). */
+#define GEVD_OPT_STAGES 9
 
 /* Precision forms (GEVD_OPT_PRECISION) of gevd_solve, gevd_solve_resident
  * and gevd_eigh.  FP32_REFINE: the products of the full -> band reduction

@@ -16,6 +16,7 @@ struct gevd_ctx {
     int panel_persist = 1; // GEVD_OPT_PANEL
     int persist_now = 0;   // the current call holds the persistent panel route (PanelLease)
     int gemm_tile = -1;    // GEVD_OPT_GEMM_TILE
+    int stages = 2;        // GEVD_OPT_STAGES
     char* ws = nullptr;  // workspace (device)
     size_t ws_bytes = 0;
     int* flags = nullptr;  // small device status area

@@ -118,9 +118,32 @@ size_t band_ws_bytes(int n, int b) {
     return carve_eigh<T>(nullptr, n, 1, b, 0, nullptr) + 256;
 }
 
+// one-stage route: sytrd1's workspace (reflectors), its back-transformation
+// scratch, d, e, the D&C eigenvectors and scratch
+template <typename T>
+size_t carve_eigh1(char* base, int n, int nev, int leaf, T** s1, T** bk, double** d, double** e, double** Zr,
+                   char** dc) {
+    Carve c{base};
+    T* a = c.take<T>(sytrd1_ws_elems<T>(n));
+    T* b = c.take<T>(sytrd1_back_ws_elems<T>(n, nev));
+    double* dd = c.take<double>(n);
+    double* ee = c.take<double>(n);
+    double* zr = c.take<double>((size_t)n * nev);
+    char* dw = c.take<char>(stedc_ws_bytes(n, nev, leaf));
+    if (s1) *s1 = a;
+    if (bk) *bk = b;
+    if (d) *d = dd;
+    if (e) *e = ee;
+    if (Zr) *Zr = zr;
+    if (dc) *dc = dw;
+    return c.off;
+}
+
 template <typename T>
 size_t eigh_ws_bytes(int n, int nev, int b, int leaf, int prec) {
-    return carve_eigh<T>(nullptr, n, nev, b, leaf, nullptr, prec) + 256;
+    return std::max(carve_eigh<T>(nullptr, n, nev, b, leaf, nullptr, prec),
+                    carve_eigh1<T>(nullptr, n, nev, leaf, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr)) +
+           256;
 }
 
 template <typename T>
@@ -133,6 +156,12 @@ int band_run(const StageCtx& c, int n, T* A, long lda, T* Bd, long ldb, char* ws
 
 template <typename T>
 int tridiag_run(const StageCtx& c, int n, T* A, long lda, double* d, double* e, char* ws) {
+    if (c.stages == 1) {
+        T* s1;
+        double *dd, *ee;
+        carve_eigh1<T>(ws, n, 1, c.leaf, &s1, nullptr, &dd, &ee, nullptr, nullptr);
+        return sytrd1<T>(c, n, A, lda, d, e ? e : ee, s1);
+    }
     EighWs<T> w;
     carve_eigh<T>(ws, n, 1, c.b, c.leaf, &w);
     int rc = he2hb<T>(c, n, A, lda, w.R1, w.Bw, w.ldw, w.he_work);
@@ -141,8 +170,30 @@ int tridiag_run(const StageCtx& c, int n, T* A, long lda, double* d, double* e, 
     return hb2st<T>(c, n, w.Bw, w.ldw, w.R2, d, ee, w.sync_area);
 }
 
+// One-stage route (c.stages == 1): Householder tridiagonalisation,
+// divide-and-conquer, one back-transformation.  FP64 throughout.
+template <typename T>
+int eigh1_run(const StageCtx& c, int n, int nev, T* A, long lda, double* eval, T* Z, long ldz, char* ws) {
+    T *s1, *bk;
+    double *d, *e, *Zr;
+    char* dc;
+    carve_eigh1<T>(ws, n, nev, c.leaf, &s1, &bk, &d, &e, &Zr, &dc);
+    int rc = sytrd1<T>(c, n, A, lda, d, e, s1);
+    if (rc) return rc;
+    c.phase(GEVD_PH_TRIDIAG);
+    c.phase(GEVD_PH_SOLVE);
+    if ((rc = stedc_run(c, n, nev, d, e, eval, Zr, n, dc))) return rc;
+    c.phase(GEVD_PH_BACK2);
+    if (is_cplx<T>::value) rc = real_to_scalar_z(c.st, n, nev, Zr, n, reinterpret_cast<zdouble*>(Z), ldz);
+    else rc = real_to_scalar_d(c.st, n, nev, Zr, n, reinterpret_cast<double*>(Z), ldz);
+    if (rc) return rc;
+    c.phase(GEVD_PH_BACK1);
+    return sytrd1_back<T>(c, n, nev, s1, Z, ldz, bk);
+}
+
 template <typename T>
 int eigh_run(const StageCtx& c, int n, int nev, T* A, long lda, double* eval, T* Z, long ldz, char* ws) {
+    if (c.stages == 1) return eigh1_run<T>(c, n, nev, A, lda, eval, Z, ldz, ws);
     EighWs<T> w;
     carve_eigh<T>(ws, n, nev, c.b, c.leaf, &w, c.prec);
     int rc = 0;

@@ -134,6 +134,7 @@ struct PanelLease {
 // bound kernels running on the handle's stream at the same time.
 void attach_aux(gevd_ctx* h, StageCtx& sc) {
     sc.panel_persist = h->persist_now;
+    sc.stages = h->stages;
     if (!h->aux) {
         int ncu = 0;
         if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h->device) != hipSuccess) ncu = 0;
@@ -559,6 +560,10 @@ int gevd_set_option(gevd_handle h, int option, int value) {
         case GEVD_OPT_PANEL:
             if (value != 0 && value != 1) return -3;
             h->panel_persist = value;
+            return 0;
+        case GEVD_OPT_STAGES:
+            if (value != 0 && value != 1 && value != 2) return -3;
+            h->stages = value == 1 ? 1 : 2;
             return 0;
         case GEVD_OPT_GEMM_TILE:
             if (value < -1 || value > 8) return -3;

@@ -20,6 +20,9 @@ struct StageCtx {
     // 1: one persistent launch per full -> band panel (needs its grid
     // resident at once); 0: one launch per panel column
     int panel_persist = 1;
+    // 1: one-stage Householder tridiagonalisation (sytrd.hip) instead of
+    // full -> band -> tridiagonal
+    int stages = 2;
     // optional second stream and two events (owned by the handle): the
     // full -> band reduction runs each trailing update beside the next
     // panel's factorization
@@ -97,6 +100,15 @@ template <typename T>
 int back_band(const StageCtx& c, const BandRefl<T>& R, int nev, T* Z, long ldz, T* work);
 template <typename T>
 size_t back_band_ws_elems(int n, int nev, int b);
+// One-stage tridiagonalisation and its back-transformation (sytrd.hip).
+template <typename T>
+size_t sytrd1_ws_elems(int n);
+template <typename T>
+size_t sytrd1_back_ws_elems(int n, int nev);
+template <typename T>
+int sytrd1(const StageCtx& c, int n, T* A, long lda, double* d, double* e, T* work);
+template <typename T>
+int sytrd1_back(const StageCtx& c, int n, int nev, const T* work1, T* Z, long ldz, T* work);
 // FP64 refinement of k approximate eigenpairs (refine.hip).
 template <typename T>
 size_t refine_ws_elems(int n, int k);

@@ -25,6 +25,7 @@ SO_PATH = os.path.join(_HERE, "libgevd.so")
 
 GEVD_REAL, GEVD_COMPLEX = 0, 1
 OPT_BAND, OPT_TIMING, OPT_LEAF, OPT_KSTATS, OPT_PRECISION, OPT_REFINE, OPT_PANEL, OPT_GEMM_TILE = 1, 2, 3, 4, 5, 6, 7, 8
+OPT_STAGES = 9
 PREC_FP64, PREC_FP32_REFINE = 0, 1
 KFAMILIES = ("gemm", "panel", "chase", "backchase", "dc", "other", "small", "gemm32")
 SMALL_MAX = 512
@@ -159,11 +160,13 @@ class Solver:
     calls.  Work goes to the current torch stream of that device."""
 
     def __init__(self, device=None, band: int = 0, leaf: int = 0, timing: bool = False, kstats: bool = False,
-                 precision: str = "fp64", refine: int = 2, persistent_panel: bool = True, gemm_tile: int = -1):
+                 precision: str = "fp64", refine: int = 2, persistent_panel: bool = True, gemm_tile: int = -1,
+                 stages: int = 2):
         """persistent_panel=False: one launch per full -> band panel column
         instead of one persistent launch per panel (for several solves
         sharing the device).  gemm_tile >= 0 forces one matrix-product tile
-        (GEVD_OPT_GEMM_TILE)."""
+        (GEVD_OPT_GEMM_TILE).  stages=1 tridiagonalises in one stage
+        (GEVD_OPT_STAGES)."""
         L = load()
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else
                                    torch.device(device).index or 0)
@@ -182,6 +185,8 @@ class Solver:
             _check(L.gevd_set_option(h, OPT_PANEL, 0), "gevd_set_option")
         if gemm_tile >= 0:
             _check(L.gevd_set_option(h, OPT_GEMM_TILE, gemm_tile), "gevd_set_option")
+        if stages != 2:
+            _check(L.gevd_set_option(h, OPT_STAGES, stages), "gevd_set_option")
         self.set_precision(precision, refine)
 
     def set_kstats(self, on: bool):
