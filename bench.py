@@ -219,6 +219,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="c2", choices=sorted(CONFIGS))
     ap.add_argument("--band", type=int, default=0)
+    ap.add_argument("--stages", type=int, default=2, choices=(1, 2),
+                    help="tridiagonalisation: 2 = full -> band -> tridiagonal, 1 = one-stage Householder")
+    ap.add_argument("--frac", type=float, default=None, help="override the wanted fraction (1.0 = all pairs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32+refine comparison")
     ap.add_argument("--no-serving", action="store_true", help="skip the batched and serving legs")
@@ -241,6 +244,11 @@ def main():
     from paper_2502_02460_amd import gevd, synth
 
     n, cplx, smin, frac, seed, label = CONFIGS[args.config]
+    if args.frac is not None:
+        frac = args.frac
+        label = label.split(",")[0] + ", wanted fraction %g" % frac + "," + ",".join(label.split(",")[2:])
+    if args.stages == 1:
+        label += ", one-stage tridiagonalisation"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     t0 = time.time()
@@ -253,7 +261,7 @@ def main():
           file=sys.stderr, flush=True)
     # the timed steps run without per-launch events; one more step with the
     # kernel-family accounting on gives the roofline figures
-    solver = gevd.Solver(dev, band=args.band, timing=True, kstats=False)
+    solver = gevd.Solver(dev, band=args.band, timing=True, kstats=False, stages=args.stages)
     H = torch.empty_like(H0)
     S = torch.empty_like(S0)
     C = torch.empty((k, n), dtype=H0.dtype, device=dev).mT
@@ -317,8 +325,8 @@ def main():
         "dtype": "c128" if cplx else "f64",
         "data": "synthetic",
         "config": {"workload": label if args.inputs == "paper" else label + " (plain inputs)", "n": n, "nev": k,
-                   "complex": cplx, "sigma_min": smin,
-                   "band": solver.band_width(n, H0.dtype)},
+                   "complex": cplx, "sigma_min": smin, "stages": args.stages,
+                   "band": solver.band_width(n, H0.dtype) if args.stages == 2 else None},
         "p50_s": round(p50, 4),
         "p99_s": round(p99, 4),
         "phases_ms": {kk: round(v, 2) for kk, v in ph.items()},

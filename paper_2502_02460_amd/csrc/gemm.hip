@@ -68,6 +68,9 @@ struct GemmP {
     T alpha, beta;
     int kmode, tmode;
     int tiles_m;
+    int rev;     // bit 0: tile rows in descending order, bit 1: tile columns descending
+    int amask;   // structural zeros of op(A): 1 for l < i, 2 for l > i (from kmode)
+    int bmask;   // structural zeros of op(B): 1 for l > j, 2 for l < j
     int bm, bn;  // workgroup tile (for tile-level triangle tests)
     long long sA, sB, sC;
     int splitk;
@@ -79,8 +82,8 @@ struct GemmP {
 template <typename T, int OPA>
 __device__ inline T load_opA(const GemmP<T>& p, const T* A, int i, int l, int kend) {
     if (i >= p.m || l >= kend) return zero_of<T>();
-    if ((p.kmode == K_A_UPPER || p.kmode == K_AU_BU) && l < i) return zero_of<T>();
-    if ((p.kmode == K_A_LOWER || p.kmode == K_AL_BU) && l > i) return zero_of<T>();
+    if (p.amask == 1 && l < i) return zero_of<T>();
+    if (p.amask == 2 && l > i) return zero_of<T>();
     if (OPA == OP_N) {
         if (p.kmode == K_A_HERM_LOWER && i < l) return conjg(A[IDX(l, i, p.lda)]);
         return A[IDX(i, p.amap ? p.amap[l] : l, p.lda)];
@@ -92,8 +95,8 @@ __device__ inline T load_opA(const GemmP<T>& p, const T* A, int i, int l, int ke
 template <typename T, int OPB>
 __device__ inline T load_opB(const GemmP<T>& p, const T* B, int l, int j, int kend) {
     if (j >= p.n || l >= kend) return zero_of<T>();
-    if ((p.kmode == K_B_UPPER || p.kmode == K_AU_BU || p.kmode == K_AL_BU) && l > j) return zero_of<T>();
-    if (p.kmode == K_B_LOWER && l < j) return zero_of<T>();
+    if (p.bmask == 1 && l > j) return zero_of<T>();
+    if (p.bmask == 2 && l < j) return zero_of<T>();
     if (OPB == OP_N) return B[IDX(l, j, p.ldb)];
     T v = B[IDX(j, l, p.ldb)];
     return OPB == OP_C ? conjg(v) : v;
@@ -107,12 +110,17 @@ __device__ inline T load_opB(const GemmP<T>& p, const T* B, int l, int j, int ke
 // XCD at a time cover a compact block of C and share their A and B panels.
 // Products whose tiles differ in work (one triangle of tiles computed, or a
 // triangular operand clipping the inner range) keep the plain column-major
-// order: contiguous ranges would load some XCDs far more than others.
+// order: contiguous ranges would load some XCDs far more than others.  Their
+// rows or columns run in descending order where that puts the tiles with
+// the longest inner range first (workgroups are dispatched in index order,
+// so the largest jobs start first and the short ones fill the tail).
 constexpr int NXCD = 8, GM = 8;
-__device__ inline void tile_of(int bid, int nblocks, int tiles_m, bool swizzle, int& ti, int& tj) {
+__device__ inline void tile_of(int bid, int nblocks, int tiles_m, bool swizzle, int rev, int& ti, int& tj) {
     if (!swizzle) {
         ti = bid % tiles_m;
         tj = bid / tiles_m;
+        if (rev & 1) ti = tiles_m - 1 - ti;
+        if (rev & 2) tj = nblocks / tiles_m - 1 - tj;
         return;
     }
     const int per = nblocks / NXCD;
@@ -143,7 +151,7 @@ __global__ __launch_bounds__(WAVE * WGM * WGN) void gemm_kernel(GemmP<T> p) {
 
     int ti, tj;
     tile_of(blockIdx.x, gridDim.x, p.tiles_m,
-            p.tmode == T_ALL && (p.kmode == K_FULL || p.kmode == K_A_HERM_LOWER), ti, tj);
+            p.tmode == T_ALL && (p.kmode == K_FULL || p.kmode == K_A_HERM_LOWER), p.rev, ti, tj);
     // triangle modes skip tiles whose every element lies on the other side
     if ((p.tmode == T_UPPER_TILES || p.tmode == T_UPPER_STRICT) && ti * BM > tj * BN + BN - 1) return;
     if ((p.tmode == T_LOWER_TILES || p.tmode == T_LOWER_STRICT) && ti * BM + BM - 1 < tj * BN) return;
@@ -490,6 +498,13 @@ int gemm(hipStream_t st, int opA, int opB, int m, int n, int k, T alpha, const T
     p.A = A; p.lda = lda; p.B = B; p.ldb = ldb; p.C = C; p.ldc = ldc;
     p.alpha = alpha; p.beta = beta;
     p.kmode = kmode; p.tmode = tmode;
+    // longest inner ranges first: the range grows with the tile row for
+    // K_A_LOWER / K_AL_BU and with the tile column for K_B_UPPER / K_AU_BU /
+    // K_AL_BU (K_A_UPPER and K_B_LOWER shrink along them: ascending already)
+    p.rev = ((kmode == K_A_LOWER || kmode == K_AL_BU) ? 1 : 0) |
+            ((kmode == K_B_UPPER || kmode == K_AU_BU || kmode == K_AL_BU) ? 2 : 0);
+    p.amask = (kmode == K_A_UPPER || kmode == K_AU_BU) ? 1 : (kmode == K_A_LOWER || kmode == K_AL_BU) ? 2 : 0;
+    p.bmask = (kmode == K_B_UPPER || kmode == K_AU_BU || kmode == K_AL_BU) ? 1 : kmode == K_B_LOWER ? 2 : 0;
     const int cfg = pick_tile(m, n, is_cplx<T>::value, splitk, batch.count, tmode);
     const int bm = TILE_BM[cfg], bn = TILE_BN[cfg];
     p.bm = bm;

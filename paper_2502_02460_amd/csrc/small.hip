@@ -3,7 +3,7 @@
 // paper's introduction and its usability section, when each one is far too
 // small to fill the GPU.  Each workgroup takes the next problem from an
 // atomic queue and runs the whole solve of the paper's section on the
-// generalized eigenproblem (Eqs. (2)-(4)) on it:
+// generalized eigenproblem (its Eq. (2), by Cholesky reduction) on it:
 //   1. Cholesky S = U^H U (blocked left-looking, L = U^H kept too),
 //   2. A = U^{-H} H U^{-1} by two row-wise triangular solves,
 //   3. one-stage Householder tridiagonalisation (for small orders the
