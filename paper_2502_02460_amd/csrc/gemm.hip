@@ -196,26 +196,85 @@ __global__ __launch_bounds__(WAVE * WGM * WGN) void gemm_kernel(GemmP<T> p) {
     // slab.  (A second register set for two slabs of lead costs occupancy
     // and measured slower on gfx950.)
     T ra[LA], rb[LB];
+    // A slab needs no per-element test when it lies inside the matrix and
+    // inside the inner range, and every element is on the stored side of a
+    // structural-zero mask (uniform per slab: a scalar branch)
+    const bool a_plain = p.kmode != K_A_HERM_LOWER && !p.amap && i0 + BM <= p.m;
+    const bool a_herm = p.kmode == K_A_HERM_LOWER && !p.amap && i0 + BM <= p.m;
+    const bool b_plain = j0 + BN <= p.n;
     auto gload = [&](int kt) {
         // Hermitian A from its lower triangle: a slab entirely above the
         // diagonal is read transposed with the coalesced (row-contiguous)
         // mapping; other slabs element by element.
         const bool herm_up = p.kmode == K_A_HERM_LOWER && i0 + BM - 1 < kt;
+        const bool kin = kt + BK <= kend;
+        const bool a_fast = a_plain && kin && (p.amask == 0 || (p.amask == 1 && kt >= i0 + BM - 1) ||
+                                               (p.amask == 2 && kt + BK - 1 <= i0));
+        const bool b_fast = b_plain && kin && (p.bmask == 0 || (p.bmask == 1 && kt + BK - 1 <= j0) ||
+                                               (p.bmask == 2 && kt >= j0 + BN - 1));
+        // Hermitian A read from its lower triangle: a slab wholly below the
+        // diagonal is read as stored, one wholly above it conjugate-transposed
+        const bool h_below = a_herm && kin && kt + BK - 1 <= i0;
+        const bool h_above = a_herm && kin && herm_up;
+        if (OPA == OP_N && h_below) {
 #pragma unroll
-        for (int r = 0; r < LA; ++r) {
-            const int e = t + r * NTK;
-            int ii, ll;
-            if (OPA == OP_N && !herm_up) { ii = e % BM; ll = e / BM; }
-            else { ii = e / BK; ll = e % BK; }
-            ra[r] = load_opA<T, OPA>(p, A, i0 + ii, kt + ll, kend);
+            for (int r = 0; r < LA; ++r) {
+                const int e = t + r * NTK;
+                ra[r] = A[IDX(i0 + e % BM, kt + e / BM, p.lda)];
+            }
+        } else if (OPA == OP_N && h_above) {
+#pragma unroll
+            for (int r = 0; r < LA; ++r) {
+                const int e = t + r * NTK;
+                ra[r] = conjg(A[IDX(kt + e % BK, i0 + e / BK, p.lda)]);
+            }
+        } else if (a_fast) {
+#pragma unroll
+            for (int r = 0; r < LA; ++r) {
+                const int e = t + r * NTK;
+                int ii, ll;
+                if (OPA == OP_N) { ii = e % BM; ll = e / BM; }
+                else { ii = e / BK; ll = e % BK; }
+                if (OPA == OP_N) {
+                    ra[r] = A[IDX(i0 + ii, kt + ll, p.lda)];
+                } else {
+                    const T v = A[IDX(kt + ll, i0 + ii, p.lda)];
+                    ra[r] = OPA == OP_C ? conjg(v) : v;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < LA; ++r) {
+                const int e = t + r * NTK;
+                int ii, ll;
+                if (OPA == OP_N && !herm_up) { ii = e % BM; ll = e / BM; }
+                else { ii = e / BK; ll = e % BK; }
+                ra[r] = load_opA<T, OPA>(p, A, i0 + ii, kt + ll, kend);
+            }
         }
+        if (b_fast) {
 #pragma unroll
-        for (int r = 0; r < LB; ++r) {
-            const int e = t + r * NTK;
-            int jj, ll;
-            if (OPB == OP_N) { ll = e % BK; jj = e / BK; }
-            else { jj = e % BN; ll = e / BN; }
-            rb[r] = load_opB<T, OPB>(p, B, kt + ll, j0 + jj, kend);
+            for (int r = 0; r < LB; ++r) {
+                const int e = t + r * NTK;
+                int jj, ll;
+                if (OPB == OP_N) { ll = e % BK; jj = e / BK; }
+                else { jj = e % BN; ll = e / BN; }
+                if (OPB == OP_N) {
+                    rb[r] = B[IDX(kt + ll, j0 + jj, p.ldb)];
+                } else {
+                    const T v = B[IDX(j0 + jj, kt + ll, p.ldb)];
+                    rb[r] = OPB == OP_C ? conjg(v) : v;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < LB; ++r) {
+                const int e = t + r * NTK;
+                int jj, ll;
+                if (OPB == OP_N) { ll = e % BK; jj = e / BK; }
+                else { jj = e % BN; ll = e / BN; }
+                rb[r] = load_opB<T, OPB>(p, B, kt + ll, j0 + jj, kend);
+            }
         }
     };
     auto sstore = [&](int buf, int kt) {

@@ -11,6 +11,7 @@ columns, and its S-orthonormality.  The GPU test holds the solver to
 max(1e-11, 2x) these values on the same input.
 
     python tests/golden/make_fullsize.py            # minutes (n = 8192: ~30 min on 8 cores)
+    python tests/golden/make_fullsize.py --floors   # adds each input's FP64 floor (tests/floors.py)
 """
 from __future__ import annotations
 
@@ -27,6 +28,7 @@ if ROOT not in sys.path:
 
 import oracle  # noqa: E402
 from paper_2502_02460_amd import synth  # noqa: E402
+from tests import floors  # noqa: E402
 
 OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "fullsize_oracle.json")
 # (n, seed) of the real commuting full-size cases; lowest 30 %, sigma_min 1e-6
@@ -48,12 +50,25 @@ def main() -> int:
     if os.path.exists(OUT):
         with open(OUT) as f:
             out = json.load(f).get("cases", {})
-    only = [int(a) for a in sys.argv[1:]]
+    only = [int(a) for a in sys.argv[1:] if a != "--floors"]
+    floors_only = "--floors" in sys.argv[1:]
     for n, seed in CASES:
         if only and n not in only:
             continue
         t = time.time()
         p, sha = synth.pinned_problem("commuting", n, False, 1e-6, seed, 0.3)
+        if floors_only and key(n, seed) in out:
+            # the input's FP64 floor (tests/floors.py) on top of the stored entry
+            fl = floors.floor(p.H, p.S, p.k, norm_h=float(abs(p.lam).max()), norm_s=float(p.sigma.max()))
+            out[key(n, seed)].update({"F": fl["F"], "F_normwise": fl["F_normwise"]})
+            print(key(n, seed), fl, flush=True)
+            doc = {"what": "CPU oracle accuracy on the full-size commuting pencils (tests/golden/make_fullsize.py)",
+                   "command": "python tests/golden/make_fullsize.py; python tests/golden/make_fullsize.py --floors",
+                   "cases": out}
+            with open(OUT + ".tmp", "w") as f:
+                json.dump(doc, f, indent=1)
+            os.replace(OUT + ".tmp", OUT)
+            continue
         w, C, _ = oracle.gevd(p.H, p.S, p.k)
         nh, ns = float(np.abs(p.lam).max()), float(p.sigma.max())
         R = p.H @ C - (p.S @ C) * w[None, : p.k]
@@ -70,7 +85,8 @@ def main() -> int:
                              "oracle_seconds": round(time.time() - t, 1)}
         print(key(n, seed), json.dumps(out[key(n, seed)]), flush=True)
         doc = {"what": "CPU oracle accuracy on the full-size commuting pencils (tests/golden/make_fullsize.py)",
-               "command": "python tests/golden/make_fullsize.py", "cases": out}
+               "command": "python tests/golden/make_fullsize.py; python tests/golden/make_fullsize.py --floors",
+               "cases": out}
         with open(OUT + ".tmp", "w") as f:
             json.dump(doc, f, indent=1)
         os.replace(OUT + ".tmp", OUT)
