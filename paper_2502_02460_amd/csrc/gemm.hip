@@ -199,7 +199,7 @@ __global__ __launch_bounds__(WAVE * WGM * WGN) void gemm_kernel(GemmP<T> p) {
     // A slab needs no per-element test when it lies inside the matrix and
     // inside the inner range, and every element is on the stored side of a
     // structural-zero mask (uniform per slab: a scalar branch)
-    const bool a_plain = p.kmode != K_A_HERM_LOWER && !p.amap && i0 + BM <= p.m;
+    const bool a_plain = p.kmode != K_A_HERM_LOWER && i0 + BM <= p.m;
     const bool a_herm = p.kmode == K_A_HERM_LOWER && !p.amap && i0 + BM <= p.m;
     const bool b_plain = j0 + BN <= p.n;
     auto gload = [&](int kt) {
@@ -236,7 +236,7 @@ __global__ __launch_bounds__(WAVE * WGM * WGN) void gemm_kernel(GemmP<T> p) {
                 if (OPA == OP_N) { ii = e % BM; ll = e / BM; }
                 else { ii = e / BK; ll = e % BK; }
                 if (OPA == OP_N) {
-                    ra[r] = A[IDX(i0 + ii, kt + ll, p.lda)];
+                    ra[r] = A[IDX(i0 + ii, p.amap ? p.amap[kt + ll] : kt + ll, p.lda)];
                 } else {
                     const T v = A[IDX(kt + ll, i0 + ii, p.lda)];
                     ra[r] = OPA == OP_C ? conjg(v) : v;
