@@ -75,7 +75,8 @@ def cpu_model() -> str:
 def measured_traffic(config: str, family: str, band: int):
     """HBM bytes per launch of a kernel family from the committed PMC
     summary (profiles/), or None when there is none for this workload and
-    band width, or the kernel source changed since the counters were taken."""
+    band width, or the kernel's source or a caller that fixes its launch
+    shapes changed since the counters were taken."""
     import hashlib
 
     path = os.path.join(ROOT, "profiles", "%s_family_%s_traffic.json" % (family, config))
@@ -85,12 +86,14 @@ def measured_traffic(config: str, family: str, band: int):
         rec = json.load(f)
     if rec.get("band") != band:
         return None
-    src = os.path.join(ROOT, rec["source"])
-    if not os.path.exists(src):
-        return None
-    with open(src, "rb") as f:
-        if hashlib.sha256(f.read()).hexdigest() != rec["source_sha256"]:
+    # the kernel's source and its callers' (which fix the launch shapes)
+    for rel, sha in rec["sources"].items():
+        src = os.path.join(ROOT, rel)
+        if not os.path.exists(src):
             return None
+        with open(src, "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != sha:
+                return None
     return rec["hbm_bytes_per_launch"]
 
 
