@@ -356,6 +356,15 @@ int gevd_solve_batched(gevd_handle h, int count, const gevd_problem *probs, int 
  * the batch was created.  Errors: as gevd_solve_batched. */
 int gevd_batch_create(gevd_handle h, int count, const gevd_problem *probs, gevd_batch *b);
 int gevd_batch_run(gevd_batch b, int *info);
+/* gevd_batch_run without any host synchronisation: replays the graph on the
+ * handle's current stream, then copies the per-problem status (count ints,
+ * problem i at info_dev[i], values as for gevd_solve_batched) into the
+ * caller's device array on the same stream.  Returns once both are
+ * enqueued; the statuses, eigenvalues and vectors are valid when the stream
+ * reaches that point (an event, or any later work on the stream, may consume
+ * them).  info_dev is the caller's, count ints in device memory.  Errors: -1
+ * null batch, -2 null info_dev, GEVD_E_HIP. */
+int gevd_batch_run_async(gevd_batch b, int *info_dev);
 int gevd_batch_destroy(gevd_batch b);
 
 /* Launch shape of the bucket holding order n: threads per workgroup (64,

@@ -230,7 +230,7 @@ int build(gevd_ctx* h, int count, const gevd_problem* probs, bool graphed, gevd_
     return 0;
 }
 
-int run(gevd_batch_s* b, int* info) {
+int run(gevd_batch_s* b, int* info, int* info_dev = nullptr) {
     gevd_ctx* h = b->h;
     GEVD_HIP(hipSetDevice(h->device));
     {
@@ -248,6 +248,8 @@ int run(gevd_batch_s* b, int* info) {
         }
     }
     g_kstats = nullptr;
+    if (info_dev)
+        GEVD_HIP(hipMemcpyAsync(info_dev, b->info, sizeof(int) * b->count, hipMemcpyDeviceToDevice, h->stream));
     if (info) {
         GEVD_HIP(hipMemcpyAsync(info, b->info, sizeof(int) * b->count, hipMemcpyDeviceToHost, h->stream));
         GEVD_HIP(hipStreamSynchronize(h->stream));
@@ -274,6 +276,12 @@ int gevd_batch_create(gevd_handle h, int count, const gevd_problem* probs, gevd_
 int gevd_batch_run(gevd_batch b, int* info) {
     if (!b) return -1;
     return run(b, info);
+}
+
+int gevd_batch_run_async(gevd_batch b, int* info_dev) {
+    if (!b) return -1;
+    if (!info_dev) return -2;
+    return run(b, nullptr, info_dev);
 }
 
 int gevd_batch_destroy(gevd_batch b) {

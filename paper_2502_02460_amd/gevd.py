@@ -109,6 +109,7 @@ def load():
         L.gevd_solve_batched_noalloc.argtypes = [P, I, PP, IP]
         L.gevd_batch_create.argtypes = [P, I, PP, ctypes.POINTER(P)]
         L.gevd_batch_run.argtypes = [P, IP]
+        L.gevd_batch_run_async.argtypes = [P, P]
         L.gevd_batch_destroy.argtypes = [P]
         L.gevd_set_batch_shape.argtypes = [P, I, I, I, I]
         L.gevd_get_batch_shape.argtypes = [P, I, I, IP, IP]
@@ -526,6 +527,18 @@ class Batch:
             return list(info)
         _check(load().gevd_batch_run(self._b, None), "gevd_batch_run")
         return None
+
+    def run_async(self, info_dev: torch.Tensor):
+        """Replay and copy the per-problem status into info_dev (int32 device
+        tensor of one entry per problem) on the solver's current stream; no
+        host synchronisation."""
+        if info_dev.dtype != torch.int32 or not info_dev.is_cuda or not info_dev.is_contiguous():
+            raise ValueError("info_dev must be a contiguous int32 device tensor")
+        if info_dev.numel() < len(self.results):
+            raise ValueError("info_dev holds %d entries, the batch has %d problems"
+                             % (info_dev.numel(), len(self.results)))
+        self.solver._stream()
+        _check(load().gevd_batch_run_async(self._b, ctypes.c_void_p(info_dev.data_ptr())), "gevd_batch_run_async")
 
     def close(self):
         if getattr(self, "_b", None):

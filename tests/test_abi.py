@@ -84,6 +84,8 @@ def test_batched_entry_points_validate_on_host(lib):
     assert lib.gevd_batch_create(None, 1, None, None) == -1
     lib.gevd_batch_run.argtypes = [P, P]
     assert lib.gevd_batch_run(None, None) == -1
+    lib.gevd_batch_run_async.argtypes = [P, P]
+    assert lib.gevd_batch_run_async(None, None) == -1
     lib.gevd_batch_destroy.argtypes = [P]
     assert lib.gevd_batch_destroy(None) == -1
     lib.gevd_set_batch_shape.argtypes = [P, I, I, I, I]

@@ -101,6 +101,37 @@ def test_failures_stay_local(solver):
     assert np.array_equal(host(res[0][0]), host(res[3][0]))
 
 
+def test_async_replay_status_on_device(solver):
+    """gevd_batch_run_async: no host synchronisation; the statuses land in a
+    device array on the stream (a failing problem included), the results
+    equal those of the synchronous replay bit for bit."""
+    ps = [synth.pencil(n, c, 1e-3, 91 + n, 0.5) for n, c in ((48, True), (100, False), (160, True))]
+    items = _items(ps)
+    bad_S = ps[1].S.copy()
+    bad_S[7, 7] = -1.0  # leading minor 8 is not positive definite
+    items[1] = (items[1][0], dev(bad_S), ps[1].k)
+    pristine = [(H.clone(), S.clone()) for H, S, _ in items]
+    b = solver.batch(items)
+    info_sync = b.run()
+    assert info_sync[0] == 0 and info_sync[2] == 0 and 0 < info_sync[1] <= 8
+    ref = [(host(w), host(C)) for w, C in b.results]
+    info_dev = torch.full((len(items),), -77, dtype=torch.int32, device="cuda")
+    for rep in range(2):
+        for (H, S, _), (H0, S0) in zip(items, pristine):
+            H.copy_(H0)
+            S.copy_(S0)
+        info_dev.fill_(-77)
+        b.run_async(info_dev)
+        got = info_dev.cpu().tolist()  # stream-ordered after the replay
+        assert got == info_sync, (rep, got, info_sync)
+        for i in (0, 2):
+            assert np.array_equal(host(b.results[i][0]), ref[i][0])
+            assert np.array_equal(host(b.results[i][1]), ref[i][1])
+    with pytest.raises(ValueError):
+        b.run_async(torch.zeros(len(items) - 1, dtype=torch.int32, device="cuda"))
+    b.close()
+
+
 def test_tuner_and_shapes(gpu_lib, solver):
     t, w = solver.tune_batched(torch.float64, 60, count=96)
     assert t in (64, 128, 256, 512) and w >= 1
