@@ -75,32 +75,44 @@ struct GemmP {
     long long sA, sB, sC;
     int splitk;
     T* work;
-    const int* amap;  // op(A) = A (N only): inner index l reads column amap[l]
+    const int* amap;  // op(A) = A (N only, no structural zeros): inner index l reads column amap[l]
     const int* cmap;  // output column j is stored to column cmap[j] (< 0: skipped)
 };
 
-template <typename T, int OPA>
-__device__ inline T load_opA(const GemmP<T>& p, const T* A, int i, int l, int kend) {
-    if (i >= p.m || l >= kend) return zero_of<T>();
-    if (p.amask == 1 && l < i) return zero_of<T>();
-    if (p.amask == 2 && l > i) return zero_of<T>();
-    if (OPA == OP_N) {
-        if (p.kmode == K_A_HERM_LOWER && i < l) return conjg(A[IDX(l, i, p.lda)]);
-        return A[IDX(i, p.amap ? p.amap[l] : l, p.lda)];
-    }
-    T v = A[IDX(l, i, p.lda)];
-    return OPA == OP_C ? conjg(v) : v;
-}
+// v or conj(v), chosen per element without a branch
+__device__ inline double conj_if(double v, bool) { return v; }
+__device__ inline zdouble conj_if(zdouble v, bool c) { return {v.x, c ? -v.y : v.y}; }
 
-template <typename T, int OPB>
-__device__ inline T load_opB(const GemmP<T>& p, const T* B, int l, int j, int kend) {
-    if (j >= p.n || l >= kend) return zero_of<T>();
-    if (p.bmask == 1 && l > j) return zero_of<T>();
-    if (p.bmask == 2 && l < j) return zero_of<T>();
-    if (OPB == OP_N) return B[IDX(l, j, p.ldb)];
-    T v = B[IDX(j, l, p.ldb)];
-    return OPB == OP_C ? conjg(v) : v;
+// Operand loads through a buffer resource based near the slab: a byte
+// offset at or beyond the resource's size (OOB) returns zero and touches no
+// memory, so masked elements need neither a branch nor a valid address, and
+// the compiler cannot turn the load into a conditional one.  Offsets from
+// the base stay below 2^31 bytes (checked on the host from the leading
+// dimensions).
+constexpr unsigned OOB = 0x80000000u;
+__device__ inline __amdgpu_buffer_rsrc_t rsrc_of(const void* base) {
+    // stride 0, size 2^31 - 1 bytes, 32-bit data format (raw dword access)
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, 0x7fffffff, 0x00020000);
 }
+__device__ inline double bload(double*, __amdgpu_buffer_rsrc_t r, unsigned off) {
+    typedef unsigned u2 __attribute__((ext_vector_type(2)));
+    const u2 u = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+    double v;
+    __builtin_memcpy(&v, &u, sizeof v);
+    return v;
+}
+__device__ inline zdouble bload(zdouble*, __amdgpu_buffer_rsrc_t r, unsigned off) {
+    typedef unsigned u4 __attribute__((ext_vector_type(4)));
+    const u4 u = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+    zdouble v;
+    __builtin_memcpy(&v, &u, sizeof v);
+    return v;
+}
+// Every offset from a slab's base is below 161 leading dimensions (at most
+// 128 + 16 columns of the slab, plus a row range of at most one leading
+// dimension), so leading dimensions under 2^31 / 192 bytes keep all offsets
+// below 2^31.
+constexpr long MAX_LD_BYTES = (1L << 31) / 192;
 
 
 // Output tile of a workgroup.  Workgroups are dispatched to the 8 XCDs
@@ -196,85 +208,80 @@ __global__ __launch_bounds__(WAVE * WGM * WGN) void gemm_kernel(GemmP<T> p) {
     // slab.  (A second register set for two slabs of lead costs occupancy
     // and measured slower on gfx950.)
     T ra[LA], rb[LB];
-    // A slab needs no per-element test when it lies inside the matrix and
-    // inside the inner range, and every element is on the stored side of a
-    // structural-zero mask (uniform per slab: a scalar branch)
-    const bool a_plain = p.kmode != K_A_HERM_LOWER && i0 + BM <= p.m;
-    const bool a_herm = p.kmode == K_A_HERM_LOWER && !p.amap && i0 + BM <= p.m;
-    const bool b_plain = j0 + BN <= p.n;
+    bool ca[LA], cb[LB];  // conjugate when staged (applied at the LDS store, after the loads have landed)
+    // Every thread issues its slab loads unconditionally in straight-line
+    // code (buffer loads; masked elements read zero), so that they are all in
+    // flight together and the first wait comes at the LDS store after the
+    // slab's MFMAs.  (Branches around the loads made the compiler wait for
+    // each group of loads before issuing the next.)
+    const bool herm = p.kmode == K_A_HERM_LOWER;
     auto gload = [&](int kt) {
-        // Hermitian A from its lower triangle: a slab entirely above the
-        // diagonal is read transposed with the coalesced (row-contiguous)
-        // mapping; other slabs element by element.
-        const bool herm_up = p.kmode == K_A_HERM_LOWER && i0 + BM - 1 < kt;
-        const bool kin = kt + BK <= kend;
-        const bool a_fast = a_plain && kin && (p.amask == 0 || (p.amask == 1 && kt >= i0 + BM - 1) ||
-                                               (p.amask == 2 && kt + BK - 1 <= i0));
-        const bool b_fast = b_plain && kin && (p.bmask == 0 || (p.bmask == 1 && kt + BK - 1 <= j0) ||
-                                               (p.bmask == 2 && kt >= j0 + BN - 1));
-        // Hermitian A read from its lower triangle: a slab wholly below the
-        // diagonal is read as stored, one wholly above it conjugate-transposed
-        const bool h_below = a_herm && kin && kt + BK - 1 <= i0;
-        const bool h_above = a_herm && kin && herm_up;
-        if (OPA == OP_N && h_below) {
+        // Hermitian A kept in its lower triangle: a slab wholly above the
+        // diagonal is read conjugate-transposed with the row-contiguous
+        // mapping; elsewhere element (i, l) with i < l is conj(A[l, i])
+        const bool herm_up = herm && i0 + BM - 1 < kt;
+        if (OPA == OP_N && p.amap) {
+            // the merge products' column map: columns anywhere in A, flat loads
 #pragma unroll
             for (int r = 0; r < LA; ++r) {
                 const int e = t + r * NTK;
-                ra[r] = A[IDX(i0 + e % BM, kt + e / BM, p.lda)];
-            }
-        } else if (OPA == OP_N && h_above) {
-#pragma unroll
-            for (int r = 0; r < LA; ++r) {
-                const int e = t + r * NTK;
-                ra[r] = conjg(A[IDX(kt + e % BK, i0 + e / BK, p.lda)]);
-            }
-        } else if (a_fast) {
-#pragma unroll
-            for (int r = 0; r < LA; ++r) {
-                const int e = t + r * NTK;
-                int ii, ll;
-                if (OPA == OP_N) { ii = e % BM; ll = e / BM; }
-                else { ii = e / BK; ll = e % BK; }
-                if (OPA == OP_N) {
-                    ra[r] = A[IDX(i0 + ii, p.amap ? p.amap[kt + ll] : kt + ll, p.lda)];
-                } else {
-                    const T v = A[IDX(kt + ll, i0 + ii, p.lda)];
-                    ra[r] = OPA == OP_C ? conjg(v) : v;
-                }
+                const int i = i0 + e % BM, l = kt + e / BM;
+                const bool ok = i < p.m && l < kend;
+                const int c = p.amap[ok ? l : kbeg];
+                const T v = A[ok ? IDX(i, c, p.lda) : 0];
+                ra[r] = ok ? v : zero_of<T>();
+                ca[r] = false;
             }
         } else {
+            // based at the smallest stored row and column the slab reads
+            const int rb0 = OPA == OP_N ? (herm ? min(i0, kt) : i0) : kt;
+            const int cb0 = OPA == OP_N ? (herm ? min(i0, kt) : kt) : i0;
+            const auto rs = rsrc_of(A + IDX(rb0, cb0, p.lda));
 #pragma unroll
             for (int r = 0; r < LA; ++r) {
                 const int e = t + r * NTK;
                 int ii, ll;
-                if (OPA == OP_N && !herm_up) { ii = e % BM; ll = e / BM; }
-                else { ii = e / BK; ll = e % BK; }
-                ra[r] = load_opA<T, OPA>(p, A, i0 + ii, kt + ll, kend);
+                if (OPA == OP_N) {
+                    ii = herm_up ? e / BK : e % BM;
+                    ll = herm_up ? e % BK : e / BM;
+                } else {
+                    ii = e / BK;
+                    ll = e % BK;
+                }
+                const int i = i0 + ii, l = kt + ll;
+                const bool ok = i < p.m && l < kend && !(p.amask == 1 && l < i) && !(p.amask == 2 && l > i);
+                int sr, sc;
+                bool cj;
+                if (OPA == OP_N) {
+                    const bool up = herm && i < l;
+                    sr = up ? l : i;
+                    sc = up ? i : l;
+                    cj = up;
+                } else {
+                    sr = l;
+                    sc = i;
+                    cj = OPA == OP_C;
+                }
+                const unsigned off =
+                    ok ? (unsigned)(((size_t)(sr - rb0) + (size_t)(sc - cb0) * p.lda) * sizeof(T)) : OOB;
+                ra[r] = bload((T*)nullptr, rs, off);
+                ca[r] = cj && ok;
             }
         }
-        if (b_fast) {
+        const int rb0 = OPB == OP_N ? kt : j0, cb0 = OPB == OP_N ? j0 : kt;
+        const auto rs = rsrc_of(B + IDX(rb0, cb0, p.ldb));
 #pragma unroll
-            for (int r = 0; r < LB; ++r) {
-                const int e = t + r * NTK;
-                int jj, ll;
-                if (OPB == OP_N) { ll = e % BK; jj = e / BK; }
-                else { jj = e % BN; ll = e / BN; }
-                if (OPB == OP_N) {
-                    rb[r] = B[IDX(kt + ll, j0 + jj, p.ldb)];
-                } else {
-                    const T v = B[IDX(j0 + jj, kt + ll, p.ldb)];
-                    rb[r] = OPB == OP_C ? conjg(v) : v;
-                }
-            }
-        } else {
-#pragma unroll
-            for (int r = 0; r < LB; ++r) {
-                const int e = t + r * NTK;
-                int jj, ll;
-                if (OPB == OP_N) { ll = e % BK; jj = e / BK; }
-                else { jj = e % BN; ll = e / BN; }
-                rb[r] = load_opB<T, OPB>(p, B, kt + ll, j0 + jj, kend);
-            }
+        for (int r = 0; r < LB; ++r) {
+            const int e = t + r * NTK;
+            int jj, ll;
+            if (OPB == OP_N) { ll = e % BK; jj = e / BK; }
+            else { jj = e % BN; ll = e / BN; }
+            const int j = j0 + jj, l = kt + ll;
+            const bool ok = j < p.n && l < kend && !(p.bmask == 1 && l > j) && !(p.bmask == 2 && l < j);
+            const size_t el = OPB == OP_N ? IDX(ll, jj, p.ldb) : IDX(jj, ll, p.ldb);
+            const unsigned off = ok ? (unsigned)(el * sizeof(T)) : OOB;
+            rb[r] = bload((T*)nullptr, rs, off);
+            cb[r] = OPB == OP_C && ok;
         }
     };
     auto sstore = [&](int buf, int kt) {
@@ -285,8 +292,9 @@ __global__ __launch_bounds__(WAVE * WGM * WGN) void gemm_kernel(GemmP<T> p) {
             int ii, ll;
             if (OPA == OP_N && !herm_up) { ii = e % BM; ll = e / BM; }
             else { ii = e / BK; ll = e % BK; }
-            sA[0][buf][ll][ii] = (CT)realp(ra[r]);
-            if (CX) sA[NC - 1][buf][ll][ii] = (CT)imagp(ra[r]);
+            const T v = conj_if(ra[r], ca[r]);
+            sA[0][buf][ll][ii] = (CT)realp(v);
+            if (CX) sA[NC - 1][buf][ll][ii] = (CT)imagp(v);
         }
 #pragma unroll
         for (int r = 0; r < LB; ++r) {
@@ -294,8 +302,9 @@ __global__ __launch_bounds__(WAVE * WGM * WGN) void gemm_kernel(GemmP<T> p) {
             int jj, ll;
             if (OPB == OP_N) { ll = e % BK; jj = e / BK; }
             else { jj = e % BN; ll = e / BN; }
-            sB[0][buf][ll][jj] = (CT)realp(rb[r]);
-            if (CX) sB[NC - 1][buf][ll][jj] = (CT)imagp(rb[r]);
+            const T v = conj_if(rb[r], cb[r]);
+            sB[0][buf][ll][jj] = (CT)realp(v);
+            if (CX) sB[NC - 1][buf][ll][jj] = (CT)imagp(v);
         }
     };
     auto compute = [&](int buf) {
@@ -362,38 +371,76 @@ __global__ __launch_bounds__(WAVE * WGM * WGN) void gemm_kernel(GemmP<T> p) {
         sstore(0, kbeg);
         __syncthreads();
         int buf = 0;
-        for (int kt = kbeg; kt < kend; kt += BK) {
-            const bool more = kt + BK < kend;
-            if (more) gload(kt + BK);
+        // the last slab is peeled off, so that the loop body loads and
+        // stages unconditionally (no load can be in flight across the back
+        // edge, and the compiler places no wait before the next slab's loads)
+        int kt = kbeg;
+        for (; kt + BK < kend; kt += BK) {
+            gload(kt + BK);
             compute(buf);
-            if (more) sstore(buf ^ 1, kt + BK);
+            sstore(buf ^ 1, kt + BK);
             __syncthreads();
             buf ^= 1;
         }
+        compute(buf);
     }
 
     // Epilogue.  The f64 16x16x4 MFMA leaves D[4r + lane/16][lane%16] in
     // register r of each lane (checked on gfx950); with D = op(B)^T op(A)^T
     // that is C row lane%16, C column 4r + lane/16 of the 16 x 16 block.
     const bool strict_up = p.tmode == T_UPPER_STRICT, strict_lo = p.tmode == T_LOWER_STRICT;
-    const bool use_beta = !is_zero(p.beta);
+    const bool use_beta = !is_zero(p.beta) && p.splitk <= 1;
+    // One 16-row block at a time: destinations first (with the merge
+    // products' column map), then every old value of C the block needs, all
+    // loads issued before any is used, then the stores.
 #pragma unroll
-    for (int qa = 0; qa < FA; ++qa)
+    for (int qa = 0; qa < FA; ++qa) {
+        const int row = i0 + wm * WM + qa * 16 + lane % 16;
+        int col[FB][4];
+        bool ok[FB][4];
 #pragma unroll
         for (int qb = 0; qb < FB; ++qb)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int row = i0 + wm * WM + qa * 16 + lane % 16;
                 // f32 16x16x4 differs: register r of lane l holds D[4 (l/16) + r][l%16]
-                int col = j0 + wn * WN + qb * 16 + (std::is_same<CT, float>::value ? 4 * (lane / 16) + r
-                                                                                   : 4 * r + lane / 16);
-                if (row >= p.m || col >= p.n) continue;
-                if (strict_up && row > col) continue;
-                if (strict_lo && row < col) continue;
-                if (p.cmap) {
-                    col = p.cmap[col];
-                    if (col < 0) continue;
+                const int c = j0 + wn * WN + qb * 16 + (std::is_same<CT, float>::value ? 4 * (lane / 16) + r
+                                                                                      : 4 * r + lane / 16);
+                ok[qb][r] = row < p.m && c < p.n && !(strict_up && row > c) && !(strict_lo && row < c);
+                col[qb][r] = c;
+            }
+        if (p.cmap) {
+#pragma unroll
+            for (int qb = 0; qb < FB; ++qb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int c = p.cmap[ok[qb][r] ? col[qb][r] : 0];
+                    ok[qb][r] = ok[qb][r] && c >= 0;
+                    col[qb][r] = c;
                 }
+        }
+        T old[FB][4];
+        if (use_beta && p.cmap) {
+#pragma unroll
+            for (int qb = 0; qb < FB; ++qb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) old[qb][r] = C[ok[qb][r] ? IDX(row, col[qb][r], p.ldc) : 0];
+        } else if (use_beta) {
+            const int rb0 = i0 + wm * WM + qa * 16, cb0 = j0 + wn * WN;
+            const auto rs = rsrc_of(C + IDX(rb0, cb0, p.ldc));
+#pragma unroll
+            for (int qb = 0; qb < FB; ++qb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const unsigned off =
+                        ok[qb][r] ? (unsigned)(IDX(row - rb0, col[qb][r] - cb0, p.ldc) * sizeof(T)) : OOB;
+                    old[qb][r] = bload((T*)nullptr, rs, off);
+                }
+        }
+#pragma unroll
+        for (int qb = 0; qb < FB; ++qb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                if (!ok[qb][r]) continue;
                 T v;
                 if constexpr (G3)
                     v = zdouble{accR[qa][qb][r] - accI[qa][qb][r],
@@ -401,13 +448,14 @@ __global__ __launch_bounds__(WAVE * WGM * WGN) void gemm_kernel(GemmP<T> p) {
                 else if constexpr (CX) v = zdouble{(double)accR[qa][qb][r], (double)accI[qa][qb][r]};
                 else v = (double)accR[qa][qb][r];
                 if (p.splitk > 1) {
-                    p.work[(size_t)blockIdx.z * p.m * p.n + IDX(row, col, p.m)] = v;
+                    p.work[(size_t)blockIdx.z * p.m * p.n + IDX(row, col[qb][r], p.m)] = v;
                 } else {
                     T out = p.alpha * v;
-                    if (use_beta) out = fma_s(p.beta, C[IDX(row, col, p.ldc)], out);
-                    C[IDX(row, col, p.ldc)] = out;
+                    if (use_beta) out = fma_s(p.beta, old[qb][r], out);
+                    C[IDX(row, col[qb][r], p.ldc)] = out;
                 }
             }
+    }
 }
 
 // Deterministic reduction of split-K partials: C = alpha sum_z W_z + beta C.
@@ -546,12 +594,13 @@ int gemm(hipStream_t st, int opA, int opB, int m, int n, int k, T alpha, const T
          long ldb, T beta, T* C, long ldc, int kmode, int tmode, Batch batch, int splitk, T* work, const int* amap,
          const int* cmap) {
     if (m <= 0 || n <= 0 || batch.count <= 0) return 0;
-    if (amap && opA != OP_N) return GEVD_E_STATE;
+    if (amap && (opA != OP_N || kmode != K_FULL)) return GEVD_E_STATE;
     if (!is_cplx<T>::value) {  // conjugation is the identity for real data
         if (opA == OP_C) opA = OP_T;
         if (opB == OP_C) opB = OP_T;
     }
     if (splitk > 1 && (work == nullptr || batch.count != 1 || cmap)) splitk = 1;
+    if ((long)sizeof(T) * std::max(lda, std::max(ldb, ldc)) >= MAX_LD_BYTES) return GEVD_E_STATE;
     GemmP<T> p;
     p.m = m; p.n = n; p.k = k;
     p.A = A; p.lda = lda; p.B = B; p.ldb = ldb; p.C = C; p.ldc = ldc;
