@@ -29,6 +29,7 @@ int count_panels(int n, int b) {
 }
 
 constexpr int SKB = 8;  // split of the long inner dimension in the stage-1 back-transform
+constexpr int SKM = 128;  // largest split of the b x b product that joins two panels
 
 template <typename T>
 struct EighWs {
@@ -85,31 +86,83 @@ size_t carve_eigh(char* base, int n, int nev, int b, int leaf, EighWs<T>* out, i
 }  // namespace
 
 // ---------------------------------------------------------------- stage 1 back
-// Z <- Q1 Z with Q1 = prod_p (I - V_p T_p V_p^H): panels last-first, each as
-// X = V^H Z_rows (split inner dimension), Y = T X, Z_rows -= V Y.
+// Z <- Q1 Z with Q1 = prod_p (I - V_p T_p V_p^H): panels last-first, two at
+// a time.  Panels q = p - 1 and p form one block reflector of width 2b,
+// Q_q Q_p = I - [V_q V_p'] T_c [V_q V_p']^H with V_p' = V_p below b zero
+// rows and T_c = [T_q, -T_q (V_q^H V_p') T_p; 0, T_p], applied as
+// X = V^H Z_rows (split inner dimension), Y = T_c X, Z_rows -= V Y: one pass
+// over the rows of Z per pair, with rank-2b updates.  An odd panel count
+// applies the last panel alone.
 template <typename T>
 size_t back_band_ws_elems(int n, int nev, int b) {
-    return (size_t)(2 + SKB) * b * nev + 64;
+    // X, Y (2b x nev), split-K partials (of X, or of the joining b x b
+    // product), the pair's V (n x 2b), its T (2b x 2b), two b x b products
+    const size_t part = std::max((size_t)SKB * 2 * b * nev, (size_t)SKM * b * b);
+    return (size_t)2 * 2 * b * nev + part + (size_t)2 * b * n + (size_t)6 * b * b + 64;
 }
 
 template <typename T>
 int back_band(const StageCtx& c, const BandRefl<T>& R, int nev, T* Z, long ldz, T* work) {
-    const int b = R.b, n = R.n;
+    const int b = R.b, n = R.n, b2 = 2 * b;
     T* X = work;
-    T* Y = work + (size_t)b * nev;
-    T* sk = work + (size_t)2 * b * nev;
+    T* Y = X + (size_t)b2 * nev;
+    T* sk = Y + (size_t)b2 * nev;
+    T* Vc = sk + std::max((size_t)SKB * b2 * nev, (size_t)SKM * b * b);
+    T* Tc = Vc + (size_t)b2 * n;
+    T* M = Tc + (size_t)b2 * b2;
+    T* N1 = M + (size_t)b * b;
     const T one = from_real<T>(1.0), mone = from_real<T>(-1.0), zero = zero_of<T>();
-    for (int p = R.np - 1; p >= 0; --p) {
-        const int c0 = p * b, m = n - c0 - b;
-        const T* V = R.V + R.voff(p);
-        const T* Tf = R.Tf + (size_t)p * b * b;
-        T* Zr = Z + (c0 + b);
-        int rc = gemm<T>(c.st, OP_C, OP_N, b, nev, m, one, V, m, Zr, ldz, zero, X, b, K_FULL, T_ALL, Batch(),
+    // apply the block reflector I - V Tm V^H (m x w, T upper w x w) to the rows of Z from r0
+    auto apply = [&](const T* V, const T* Tm, int m, int w, int r0) -> int {
+        T* Zr = Z + r0;
+        int rc = gemm<T>(c.st, OP_C, OP_N, w, nev, m, one, V, m, Zr, ldz, zero, X, w, K_FULL, T_ALL, Batch(),
                          m >= 1024 ? SKB : 1, sk);
         if (rc) return rc;
-        if ((rc = gemm<T>(c.st, OP_N, OP_N, b, nev, b, one, Tf, b, X, b, zero, Y, b, K_A_UPPER))) return rc;
-        if ((rc = gemm<T>(c.st, OP_N, OP_N, m, nev, b, mone, V, m, Y, b, one, Zr, ldz))) return rc;
+        if ((rc = gemm<T>(c.st, OP_N, OP_N, w, nev, w, one, Tm, w, X, w, zero, Y, w, K_A_UPPER))) return rc;
+        return gemm<T>(c.st, OP_N, OP_N, m, nev, w, mone, V, m, Y, w, one, Zr, ldz);
+    };
+    auto single = [&](int p) -> int {
+        const int m = n - p * b - b;
+        return apply(R.V + R.voff(p), R.Tf + (size_t)p * b * b, m, b, p * b + b);
+    };
+    int rc = 0;
+    int p = R.np - 1;
+    if (R.np % 2 == 1) {
+        if ((rc = single(p))) return rc;
+        --p;
     }
+    for (; p >= 1; p -= 2) {
+        const int q = p - 1;
+        const int m = n - q * b - b, m2 = m - b;  // rows of V_q and of V_p
+        if (m2 < 1) {
+            if ((rc = single(p)) || (rc = single(q))) return rc;
+            continue;
+        }
+        const T* Vq = R.V + R.voff(q);
+        const T* Vp = R.V + R.voff(p);
+        const T* Tq = R.Tf + (size_t)q * b * b;
+        const T* Tp = R.Tf + (size_t)p * b * b;
+        // V = [V_q, V_p'] (m x 2b)
+        if ((rc = copy_matrix<T>(c.st, m, b, Vq, m, Vc, m))) return rc;
+        if ((rc = set_zero<T>(c.st, b, b, Vc + (size_t)b * m, m))) return rc;
+        if ((rc = copy_matrix<T>(c.st, m2, b, Vp, m2, Vc + (size_t)b * m + b, m))) return rc;
+        // T_c: diagonal blocks T_q, T_p (only their upper triangles are read),
+        // upper-right block -T_q (V_q^H V_p') T_p
+        // one b x b output tile: the inner dimension in chunks of about 128
+        // rows, so that the product spreads over the device
+        const int skm = std::max(1, std::min(SKM, (m2 + 127) / 128));
+        if ((rc = gemm<T>(c.st, OP_C, OP_N, b, b, m2, one, Vq + b, m, Vp, m2, zero, M, b, K_FULL, T_ALL, Batch(),
+                          skm, sk)))
+            return rc;
+        if ((rc = gemm<T>(c.st, OP_N, OP_N, b, b, b, one, Tq, b, M, b, zero, N1, b, K_A_UPPER))) return rc;
+        if ((rc = gemm<T>(c.st, OP_N, OP_N, b, b, b, mone, N1, b, Tp, b, zero, Tc + (size_t)b * b2, b2,
+                          K_B_UPPER)))
+            return rc;
+        if ((rc = copy_matrix<T>(c.st, b, b, Tq, b, Tc, b2))) return rc;
+        if ((rc = copy_matrix<T>(c.st, b, b, Tp, b, Tc + (size_t)b * b2 + b, b2))) return rc;
+        if ((rc = apply(Vc, Tc, m, b2, q * b + b))) return rc;
+    }
+    if (p == 0 && (rc = single(0))) return rc;
     return 0;
 }
 

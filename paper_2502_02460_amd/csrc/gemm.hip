@@ -16,12 +16,12 @@
 // (double-buffered, one barrier per slab).  The MFMA is issued as D = op(B)^T op(A)^T so that
 // 16 lanes of a register hold 16 consecutive rows of one column of C: every
 // store instruction writes 128-byte column segments of the column-major C.
-// Complex products run on separately staged real/imaginary tiles.  The
-// eight-wave tiles with 32 x 32 wave blocks use three real MFMAs per
-// complex k-step (Gauss: P1 = re*re, P2 = im*im, P3 = (re + im)(re + im);
-// real part P1 - P2, imaginary part P3 - P1 - P2, formed once in the
-// epilogue), 3/4 of the four-product form's matrix-core work; other tiles
-// and the FP32 compute type use four (re*re - im*im, re*im + im*re).
+// Complex products run on separately staged real/imaginary tiles.  Tiles
+// with wave blocks of at most 32 x 32 use three real MFMAs per complex
+// k-step (Gauss: P1 = re*re, P2 = im*im, P3 = (re + im)(re + im); real part
+// P1 - P2, imaginary part P3 - P1 - P2, formed once in the epilogue), 3/4
+// of the four-product form's matrix-core work; larger wave blocks and the
+// FP32 compute type use four (re*re - im*im, re*im + im*re).
 //
 // Reduced-precision form: inside a Fp32Gemm scope the operands are rounded
 // to FP32 when staged into LDS and the products run on the FP32 matrix
@@ -150,7 +150,7 @@ __device__ inline void tile_of(int bid, int nblocks, int tiles_m, bool swizzle, 
 // Workgroup tile BM x BN = (WGM WM) x (WGN WN): WGM x WGN waves, each wave
 // owns WM x WN as (WM/16) x (WN/16) MFMA blocks.
 template <typename T, typename CT, int OPA, int OPB, int WM, int WN, int WGM = 2, int WGN = 2>
-__global__ __launch_bounds__(WAVE * WGM * WGN) void gemm_kernel(GemmP<T> p) {
+__global__ __launch_bounds__(WAVE * WGM * WGN) __attribute__((amdgpu_waves_per_eu(2))) void gemm_kernel(GemmP<T> p) {
     typedef typename Acc<CT>::type AccT;
     constexpr bool CX = is_cplx<T>::value;
     constexpr int NC = CX ? 2 : 1;
@@ -189,10 +189,11 @@ __global__ __launch_bounds__(WAVE * WGM * WGN) void gemm_kernel(GemmP<T> p) {
     const int lane = t % WAVE, w = t / WAVE;
     const int wm = w % WGM, wn = w / WGM;
 
-    // three-product complex form for the FP64 compute type, on the
-    // eight-wave tiles whose 32 x 32 wave blocks leave room for the third
-    // accumulator set (elsewhere it would cost occupancy or spill)
-    constexpr bool G3 = CX && std::is_same<CT, double>::value && WGM * WGN == 8 && FA * FB <= 4;
+    // three-product complex form for the FP64 compute type, on the tiles
+    // whose wave blocks (at most 32 x 32) leave room for the third
+    // accumulator set (larger ones would spill); two waves per SIMD
+    // (amdgpu_waves_per_eu) keep the four-wave tiles at two workgroups per CU
+    constexpr bool G3 = CX && std::is_same<CT, double>::value && FA * FB <= 4;
     AccT accR[FA][FB], accI[FA][FB], accX[FA][FB];
 #pragma unroll
     for (int a = 0; a < FA; ++a)
@@ -514,14 +515,17 @@ int g_tile_override = -2;  // -2: not read yet, -1: none
 }  // namespace
 thread_local int g_tile_force = -1;  // the calling handle's GEVD_OPT_GEMM_TILE (-1: automatic)
 namespace {
-// Measured on gfx950 (FP64, n = 16384 class shapes).  Complex: the
-// eight-wave 64 x 128 tile with the three-product form runs square products
-// at 60-66 TFLOP/s against 45-49 for 64 x 64, rank-2k updates at 43 against
-// 38, and 128 x 64 wins for outputs 64 wide.  Real: the eight-wave
+// Measured on gfx950 (FP64, n = 16384 class shapes, single launches).
+// Complex: the eight-wave 64 x 128 tile runs square N/N and N/C products at
+// 95 % of the FP64 peak on the method's flops (three-product form); the
+// four-wave 64 x 64 tile, also three-product and two workgroups per CU,
+// runs C/N products at 96-99 % and rank-128 updates at 68 % against 65 %
+// (its second workgroup overlaps one tile's C traffic with another's
+// products); 128 x 64 wins for outputs 64 wide.  Real: the eight-wave
 // 128 x 128 tile runs square products about 20 % faster than 64 x 64.  The
-// eight-wave tiles need enough tiles to fill the 256 CUs (one such
-// workgroup per CU), so medium products keep 64 x 64.
-int pick_tile(int m, int n, bool cx, int splitk, int batch, int tmode) {
+// large tiles need enough of them to fill the 256 CUs, so medium products
+// keep 64 x 64.
+int pick_tile(int m, int n, int k, int opA, bool cx, int splitk, int batch, int tmode) {
     if (g_tile_override == -2) {
         const char* e = getenv("GEVD_GEMM_TILE");
         g_tile_override = e ? atoi(e) : -1;
@@ -536,6 +540,10 @@ int pick_tile(int m, int n, bool cx, int splitk, int batch, int tmode) {
     if (cx) {
         if (n <= 64 && m > 64) return tm * par >= 256 ? 7 : 0;
         if (m <= 64) return tn * par >= 256 ? 8 : 0;
+        // C/N products and short inner dimensions: the 64 x 64 tile, when
+        // there are enough tiles for two workgroups on every CU
+        const long long t64 = (long long)((m + 63) / 64) * ((n + 63) / 64) * par / (tri ? 2 : 1);
+        if ((opA == OP_C || k <= 256) && t64 >= 1024) return 0;
         return ((m + 63) / 64) * tn * par / (tri ? 2 : 1) >= 512 ? 8 : 0;
     }
     if (m > 64 && n > 64 && tm * tn * par / (tri ? 2 : 1) >= 512) return 6;
@@ -613,7 +621,7 @@ int gemm(hipStream_t st, int opA, int opB, int m, int n, int k, T alpha, const T
             ((kmode == K_B_UPPER || kmode == K_AU_BU || kmode == K_AL_BU) ? 2 : 0);
     p.amask = (kmode == K_A_UPPER || kmode == K_AU_BU) ? 1 : (kmode == K_A_LOWER || kmode == K_AL_BU) ? 2 : 0;
     p.bmask = (kmode == K_B_UPPER || kmode == K_AU_BU || kmode == K_AL_BU) ? 1 : kmode == K_B_LOWER ? 2 : 0;
-    const int cfg = pick_tile(m, n, is_cplx<T>::value, splitk, batch.count, tmode);
+    const int cfg = pick_tile(m, n, k, opA, is_cplx<T>::value, splitk, batch.count, tmode);
     const int bm = TILE_BM[cfg], bn = TILE_BN[cfg];
     p.bm = bm;
     p.bn = bn;
