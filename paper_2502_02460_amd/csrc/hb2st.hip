@@ -38,6 +38,44 @@ constexpr unsigned long long WAIT_LIMIT_TICKS = 120ull * 100000000ull;
 // cached lines on that XCD).
 __device__ inline int ntasks(int n, int b, int sw) { return (n - 1 - sw + b - 1) / b; }
 
+// Band blocks of a task move through buffer resources at system scope
+// (sc0 sc1, the same cache policy as sys_load / sys_store): one 64- or
+// 128-bit access per element, and an element a lane does not own gets an
+// out-of-range offset (loads return zero, stores are dropped), so the
+// accesses need no branches.  Offsets stay far below 2^31 bytes (a task's
+// blocks span 2b rows of at most 2b + 1 columns of the band storage).
+constexpr unsigned BOOB = 0x80000000u;
+constexpr int SYS_POLICY = 17;  // sc0 | sc1
+__device__ inline __amdgpu_buffer_rsrc_t band_rsrc(const void* base) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, 0x7fffffff, 0x00020000);
+}
+__device__ inline double band_load(double*, __amdgpu_buffer_rsrc_t r, unsigned off) {
+    typedef unsigned u2 __attribute__((ext_vector_type(2)));
+    const u2 u = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, SYS_POLICY);
+    double v;
+    __builtin_memcpy(&v, &u, sizeof v);
+    return v;
+}
+__device__ inline zdouble band_load(zdouble*, __amdgpu_buffer_rsrc_t r, unsigned off) {
+    typedef unsigned u4 __attribute__((ext_vector_type(4)));
+    const u4 u = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, SYS_POLICY);
+    zdouble v;
+    __builtin_memcpy(&v, &u, sizeof v);
+    return v;
+}
+__device__ inline void band_store(double v, __amdgpu_buffer_rsrc_t r, unsigned off) {
+    typedef unsigned u2 __attribute__((ext_vector_type(2)));
+    u2 u;
+    __builtin_memcpy(&u, &v, sizeof v);
+    __builtin_amdgcn_raw_buffer_store_b64(u, r, off, 0, SYS_POLICY);
+}
+__device__ inline void band_store(zdouble v, __amdgpu_buffer_rsrc_t r, unsigned off) {
+    typedef unsigned u4 __attribute__((ext_vector_type(4)));
+    u4 u;
+    __builtin_memcpy(&u, &v, sizeof v);
+    __builtin_amdgcn_raw_buffer_store_b128(u, r, off, 0, SYS_POLICY);
+}
+
 // Reflector parameters for x = (alpha, x1..): H^H x = beta e1 with beta real,
 // H = I - tau v v^H, v = (1, x1 * scale, ..); a2 = ||x1..||^2.
 template <typename T>
@@ -335,12 +373,18 @@ __global__ __launch_bounds__(64 * CW) void hb2st_kernel_wg(int n, int b, T* Bw, 
             // registers; D also goes to LDS, mirrored, for its matrix-vector
             // product.
             constexpr int KW = MAXB / CW;  // columns per lane
+            // E's columns from pr0 (t > 0), D's from r0
+            const auto rE = band_rsrc(Bw + IDX(0, max(pr0, 0), ldw));
+            const auto rD = band_rsrc(Bw + IDX(0, r0, ldw));
             T te[KW], td[KW];
 #pragma unroll
             for (int k = 0; k < KW; ++k) {
                 const int j = wv + CW * k;
-                te[k] = (t > 0 && lane < L && j < b) ? sys_load(&Bw[IDX(b + lane - j, pr0 + j, ldw)]) : zero_of<T>();
-                td[k] = (lane < L && j <= lane) ? sys_load(&Bw[IDX(lane - j, r0 + j, ldw)]) : zero_of<T>();
+                const unsigned oe =
+                    (t > 0 && lane < L && j < b) ? (unsigned)(IDX(b + lane - j, j, ldw) * sizeof(T)) : BOOB;
+                const unsigned od = (lane < L && j <= lane) ? (unsigned)(IDX(lane - j, j, ldw) * sizeof(T)) : BOOB;
+                te[k] = band_load((T*)nullptr, rE, oe);
+                td[k] = band_load((T*)nullptr, rD, od);
             }
 #pragma unroll
             for (int k = 0; k < KW; ++k) {
@@ -406,10 +450,9 @@ __global__ __launch_bounds__(64 * CW) void hb2st_kernel_wg(int n, int b, T* Bw, 
                     for (int k = 0; k < KW; ++k) {
                         const int j = wv + CW * k;
                         const T yj = lane_bcast(yv[0], 4 * k);
-                        if (lane < L && j < b) {
-                            if (j == 0) sys_store(&Bw[IDX(b + lane, pr0, ldw)], (lane == 0) ? beta : zero_of<T>());
-                            else sys_store(&Bw[IDX(b + lane - j, pr0 + j, ldw)], te[k] - cv * yj);
-                        }
+                        const T x = (j == 0) ? ((lane == 0) ? beta : zero_of<T>()) : te[k] - cv * yj;
+                        band_store(x, rE,
+                                   (lane < L && j < b) ? (unsigned)(IDX(b + lane - j, j, ldw) * sizeof(T)) : BOOB);
                     }
                 } else {
                     __syncthreads();
@@ -455,16 +498,14 @@ __global__ __launch_bounds__(64 * CW) void hb2st_kernel_wg(int n, int b, T* Bw, 
                     if (lane < L) y[lane] = yl + coef * v[lane];
                 }
                 __syncthreads();
-                if (lane < L) {
+                {
                     const T vi = v[lane], yi = y[lane];
 #pragma unroll
                     for (int k = 0; k < KW; ++k) {
                         const int j = wv + CW * k;
-                        if (j <= lane) {
-                            T x = td[k] - vi * conjg(y[j]) - yi * conjg(v[j]);
-                            if (lane == j) x = from_real<T>(realp(x));
-                            sys_store(&Bw[IDX(lane - j, r0 + j, ldw)], x);
-                        }
+                        T x = td[k] - vi * conjg(y[j]) - yi * conjg(v[j]);
+                        if (lane == j) x = from_real<T>(realp(x));
+                        band_store(x, rD, (lane < L && j <= lane) ? (unsigned)(IDX(lane - j, j, ldw) * sizeof(T)) : BOOB);
                     }
                 }
             }
