@@ -171,13 +171,14 @@ __global__ __launch_bounds__(64) void hb2st_kernel(int n, int b, T* Bw, long ldw
                     const int need = min(t + 2, ntasks(n, b, sw - 1));
                     unsigned spins = 0;
                     unsigned long long t_start = 0;
-                    // Relaxed polling at system scope: each poll reads the
-                    // counter past this XCD's L2 (the writer stores it at
-                    // system scope), so a stale cached line cannot delay it
-                    // and no acquire is needed; the band is read past the
-                    // caches too (sys_load).
-                    while (__hip_atomic_load(&progress[sw - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) < need) {
+                    // Relaxed polling, with an acquire every 64 polls: the L2
+                    // of this XCD is not coherent with the writer's, and a
+                    // relaxed load may keep hitting a stale line there until
+                    // an acquire invalidates it.  The band itself is read
+                    // past the caches (sys_load), so no fence follows.
+                    while (__hip_atomic_load(&progress[sw - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
                         if ((++spins & 63u) == 0) {
+                            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
                             const unsigned long long now = wall_clock64();
                             if (t_start == 0) t_start = now;
                             if (now - t_start > WAIT_LIMIT_TICKS ||
@@ -344,8 +345,9 @@ __global__ __launch_bounds__(64 * CW) void hb2st_kernel_wg(int n, int b, T* Bw, 
                     unsigned spins = 0;
                     unsigned long long t_start = 0;
                     // polling as in the single-wave kernel
-                    while (__hip_atomic_load(&progress[sw - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) < need) {
+                    while (__hip_atomic_load(&progress[sw - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
                         if ((++spins & 63u) == 0) {
+                            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
                             const unsigned long long now = wall_clock64();
                             if (t_start == 0) t_start = now;
                             if (now - t_start > WAIT_LIMIT_TICKS ||
