@@ -8,14 +8,17 @@
 //   2. A = U^{-H} H U^{-1} by two row-wise triangular solves,
 //   3. one-stage Householder tridiagonalisation (for small orders the
 //      one-stage method is the cheaper one, as the paper notes),
-//   4. implicit QL with the eigenvector rotations,
+//   4. all eigenvalues of the tridiagonal T by bisection and only the
+//      wanted eigenvectors by twisted factorisations (implicit QL with every
+//      eigenvector as the fallback when a vector fails its checks),
 //   5. back-transformation of the wanted vectors through the reflectors and
 //      U^{-1}.
 // Work is split so that global accesses are coalesced and the workgroup
 // rarely needs a barrier: triangular solves are one matrix row per lane;
 // the tridiagonalisation fuses the rank-2 update of one step with the
-// matrix-vector product of the next (one read+write pass per step); QL
-// rotations of a sweep are formed by one lane and applied by all; each
+// matrix-vector product of the next (one read+write pass per step); an
+// eigenvalue's bisection and an eigenvector's recurrences run on one lane;
+// QL rotations of a sweep are formed by one lane and applied by all; each
 // wanted eigenvector is back-transformed by one wave with its rows in
 // registers.
 #include "kernels.hpp"
@@ -436,12 +439,191 @@ __device__ bool ql_small(int n, double* d, double* e, double* rc, double* rs, do
 }
 
 // ---------------------------------------------------------------------------
+// 4'. The faster route for the tridiagonal problem, tried first.  All n
+// eigenvalues by bisection on Sturm counts (one eigenvalue per lane: the
+// i-th smallest is where the count of eigenvalues below x passes i), then
+// only the wanted eigenvectors, each from a twisted factorisation of
+// T - lambda I (one vector per lane): the forward pivots D+ and backward
+// pivots D- give gamma_r = D+_r + D-_r - (d_r - lambda) for every twist r,
+// and at the r where |gamma_r| is least the vector with z_r = 1 follows
+// from the two one-term recurrences z_i = -(e_i / D+_i) z_{i+1} above r and
+// z_{i+1} = -(e_i / D-_{i+1}) z_i below it.  Vectors of eigenvalues closer
+// than 1e-3 ||T|| to their neighbour (a cluster) are orthogonalised twice
+// against the earlier members of their cluster; those of separated
+// eigenvalues are orthogonal to working accuracy as computed.  Vectors are
+// kept row-major in the Z slot (entry r of vector i at Z[r n + i]) so that
+// the lanes' accesses coalesce; each one's pivots are stored in its own
+// column and overwritten by the vector.  Returns false (the caller then
+// takes the QL route) if a vector loses almost all of its norm to the
+// orthogonalisation or its residual ||T z - lambda z|| exceeds 1e-10 ||T||
+// (QL's vectors are orthogonal whatever the gaps, at O(n^3) cost).
+// ---------------------------------------------------------------------------
+__device__ inline int sturm_count(int n, const double* d, const double* e, double x, double pivmin) {
+    double q = d[0] - x;
+    if (fabs(q) < pivmin) q = -pivmin;
+    int cnt = q < 0.0;
+    for (int i = 1; i < n; ++i) {
+        q = d[i] - x - e[i - 1] * e[i - 1] / q;
+        if (fabs(q) < pivmin) q = -pivmin;
+        cnt += q < 0.0;
+    }
+    return cnt;
+}
+
+template <int NT>
+__device__ bool bisect_twist_small(int n, int nev, const double* d, const double* e, double* w, double* dots,
+                                   double* Z, double* redd, int* ctl) {
+    const int tid = threadIdx.x;
+    // Gershgorin interval and the pivot floor (every lane the same values)
+    double glo = d[0], ghi = d[0], emax2 = 0.0;
+    for (int i = 0; i < n; ++i) {
+        const double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < n ? fabs(e[i]) : 0.0);
+        glo = fmin(glo, d[i] - r);
+        ghi = fmax(ghi, d[i] + r);
+        if (i + 1 < n) emax2 = fmax(emax2, e[i] * e[i]);
+    }
+    const double tnorm = fmax(fabs(glo), fabs(ghi));
+    const double pivmin = 2.2250738585072014e-308 * fmax(1.0, emax2);
+    glo -= 2.0 * SEPS * tnorm + 2.0 * pivmin;
+    ghi += 2.0 * SEPS * tnorm + 2.0 * pivmin;
+    for (int idx = tid; idx < n; idx += NT) {
+        double lo = glo, hi = ghi;
+        for (int it = 0; it < 256; ++it) {
+            const double mid = 0.5 * (lo + hi);
+            if (!(mid > lo && mid < hi)) break;
+            if (sturm_count(n, d, e, mid, pivmin) > idx) hi = mid;
+            else lo = mid;
+            if (hi - lo <= 2.0 * SEPS * fmax(fabs(lo), fabs(hi)) + pivmin) break;
+        }
+        w[idx] = 0.5 * (lo + hi);
+    }
+    __syncthreads();
+    if (tid == 0) {  // ascending (bisections of nearly equal eigenvalues may end a rounding apart)
+        for (int i = 1; i < n; ++i) w[i] = fmax(w[i], w[i - 1]);
+        ctl[2] = 0;
+    }
+    __syncthreads();
+    const double tiny = 1e-3 * SEPS * tnorm + pivmin;
+    auto guard = [&](double x) { return fabs(x) < tiny ? (x < 0.0 ? -tiny : tiny) : x; };
+    for (int i = tid; i < nev; i += NT) {
+        const double lam = w[i];
+        double* zc = Z + i;  // entry r at zc[r n]
+        // forward pivots D+ into the vector's column
+        double dp = d[0] - lam;
+        for (int r = 0; r + 1 < n; ++r) {
+            dp = guard(dp);
+            zc[(size_t)r * n] = dp;
+            dp = d[r + 1] - lam - (e[r] / dp) * e[r];
+        }
+        zc[(size_t)(n - 1) * n] = guard(dp);
+        // backward pivots D-, and the twist with the least |gamma|
+        double dm = d[n - 1] - lam;
+        int tw = n - 1;
+        double best = fabs(zc[(size_t)(n - 1) * n]);
+        for (int r0 = n - 2; r0 >= 0; r0 -= ZC) {
+            double dpr[ZC];
+#pragma unroll
+            for (int q = 0; q < ZC; ++q) dpr[q] = r0 - q >= 0 ? zc[(size_t)(r0 - q) * n] : 0.0;
+#pragma unroll
+            for (int q = 0; q < ZC; ++q) {
+                const int r = r0 - q;
+                if (r >= 0) {
+                    dm = guard(dm);
+                    dm = d[r] - lam - (e[r] / dm) * e[r];
+                    const double g = fabs(dpr[q] + dm - (d[r] - lam));
+                    if (g < best) {
+                        best = g;
+                        tw = r;
+                    }
+                }
+            }
+        }
+        // the backward multipliers again, below the twist, into rows r + 1 > tw
+        dm = d[n - 1] - lam;
+        for (int r = n - 2; r >= tw; --r) {
+            dm = guard(dm);
+            const double u = e[r] / dm;
+            zc[(size_t)(r + 1) * n] = u;
+            dm = d[r] - lam - u * e[r];
+        }
+        // the vector, z_tw = 1
+        double z = 1.0, nrm2 = 1.0;
+        zc[(size_t)tw * n] = 1.0;
+        for (int r = tw - 1; r >= 0; --r) {
+            z = -(e[r] / zc[(size_t)r * n]) * z;
+            zc[(size_t)r * n] = z;
+            nrm2 += z * z;
+        }
+        z = 1.0;
+        for (int r = tw; r + 1 < n; ++r) {
+            z = -zc[(size_t)(r + 1) * n] * z;
+            zc[(size_t)(r + 1) * n] = z;
+            nrm2 += z * z;
+        }
+        const double sc = 1.0 / sqrt(nrm2);
+        for (int r = 0; r < n; ++r) zc[(size_t)r * n] *= sc;
+    }
+    __syncthreads();
+    // twice classical Gram-Schmidt inside clusters, one vector at a time
+    const double gaptol = 1e-3 * tnorm;
+    int c0 = 0;
+    for (int i = 1; i < nev; ++i) {
+        if (w[i] - w[i - 1] > gaptol) {
+            c0 = i;
+            continue;
+        }
+        const int m = i - c0;
+        for (int pass = 0; pass < 2; ++pass) {
+            for (int j = tid; j < m; j += NT) {
+                double acc = 0.0;
+                for (int r = 0; r < n; ++r) acc += Z[(size_t)r * n + c0 + j] * Z[(size_t)r * n + i];
+                dots[j] = acc;
+            }
+            __syncthreads();
+            for (int r = tid; r < n; r += NT) {
+                double x = Z[(size_t)r * n + i];
+                for (int j = 0; j < m; ++j) x -= dots[j] * Z[(size_t)r * n + c0 + j];
+                Z[(size_t)r * n + i] = x;
+            }
+            __syncthreads();
+        }
+        const double nrm2 = chunked_sum<NT, double>(n, [&](int r) {
+            const double x = Z[(size_t)r * n + i];
+            return x * x;
+        }, redd);
+        if (!(nrm2 > 1e-4)) {  // (also catches NaN) the vector was almost in its cluster's span
+            if (tid == 0) ctl[2] = 1;
+        } else {
+            const double sc = 1.0 / sqrt(nrm2);
+            for (int r = tid; r < n; r += NT) Z[(size_t)r * n + i] *= sc;
+        }
+        __syncthreads();
+    }
+    // residual of every vector
+    for (int i = tid; i < nev; i += NT) {
+        const double lam = w[i];
+        double res = 0.0, zm = 0.0, z0 = Z[i];
+        for (int r = 0; r < n; ++r) {
+            const double zp = r + 1 < n ? Z[(size_t)(r + 1) * n + i] : 0.0;
+            const double t = (d[r] - lam) * z0 + (r > 0 ? e[r - 1] * zm : 0.0) + (r + 1 < n ? e[r] * zp : 0.0);
+            res = fmax(res, fabs(t));
+            zm = z0;
+            z0 = zp;
+        }
+        if (!(res <= 1e-10 * tnorm + pivmin)) atomicOr(&ctl[2], 1);
+    }
+    __syncthreads();
+    return ctl[2] == 0;
+}
+
+// ---------------------------------------------------------------------------
 // 5. C[:, c] = U^{-1} Q Z[:, perm[c]]: one wave per column, rows in registers
 // (row lane + 64 q).  Q = H_0 H_1 ... H_{n-2} is applied right to left; then
 // U x = y by back substitution with columns of U (adjacent in memory).
 // ---------------------------------------------------------------------------
 template <typename T, int NT>
-__device__ void back_small(const SmallDesc& D, const T* A, const T* S, const double* Z, const Lds<T>& L) {
+__device__ void back_small(const SmallDesc& D, const T* A, const T* S, const double* Z, const Lds<T>& L,
+                           bool rowmajor) {
     const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
     const int n = D.n;
     const long lda = D.ldh, lds = D.lds, ldc = D.ldc;
@@ -452,7 +634,7 @@ __device__ void back_small(const SmallDesc& D, const T* A, const T* S, const dou
 #pragma unroll
         for (int q = 0; q < QMAX; ++q) {
             const int r = lane + q * WAVE;
-            y[q] = r < n ? from_real<T>(Z[IDX(r, zc, n)]) : zero_of<T>();
+            y[q] = r < n ? from_real<T>(Z[rowmajor ? (size_t)r * n + zc : IDX(r, zc, n)]) : zero_of<T>();
         }
         for (int j = n - 2; j >= 0; --j) {
             const T tau = L.tau[j];
@@ -564,28 +746,33 @@ __device__ void solve_one(const SmallDesc& D, double* Z, Lds<T>& L, T (*dblk)[RB
     SMALL_MARK(3);
     tridiag_small<T, NT>(H, ldh, n, L, red, redd);
     SMALL_MARK(4);
-    if (!ql_small<NT>(n, L.d, L.e, L.rc, L.rs, Z, ctl)) {
-        if (tid == 0) *D.info = GEVD_E_NOCONV;
-        return;
+    for (int i = tid; i < n; i += NT) L.perm[i] = i;
+    const bool fast = bisect_twist_small<NT>(n, D.nev, L.d, L.e, L.rc, L.rs, Z, redd, ctl);
+    if (fast) {
+        for (int i = tid; i < n; i += NT) D.eval[i] = L.rc[i];
+    } else {
+        // implicit QL with every vector (d and e are still T's)
+        if (!ql_small<NT>(n, L.d, L.e, L.rc, L.rs, Z, ctl)) {
+            if (tid == 0) *D.info = GEVD_E_NOCONV;
+            return;
+        }
+        // ascending order by rank (ties broken by index)
+        for (int i = tid; i < n; i += NT) {
+            const double di = L.d[i];
+            int rank = 0;
+            for (int k = 0; k < n; ++k) {
+                const double dk = L.d[k];
+                rank += (dk < di) || (dk == di && k < i);
+            }
+            L.perm[rank] = i;
+        }
+        __syncthreads();
+        for (int i = tid; i < n; i += NT) D.eval[i] = L.d[L.perm[i]];
     }
     SMALL_MARK(5);
-    // ascending order by rank (ties broken by index); perm starts as the
-    // identity so that every entry is a valid column even for unordered input
-    for (int i = tid; i < n; i += NT) L.perm[i] = i;
     __syncthreads();
-    for (int i = tid; i < n; i += NT) {
-        const double di = L.d[i];
-        int rank = 0;
-        for (int k = 0; k < n; ++k) {
-            const double dk = L.d[k];
-            rank += (dk < di) || (dk == di && k < i);
-        }
-        L.perm[rank] = i;
-    }
-    __syncthreads();
-    for (int i = tid; i < n; i += NT) D.eval[i] = L.d[L.perm[i]];
     SMALL_MARK(6);
-    back_small<T, NT>(D, H, S, Z, L);
+    back_small<T, NT>(D, H, S, Z, L, fast);
     __syncthreads();
     SMALL_MARK(7);
     if (tid == 0) *D.info = 0;
