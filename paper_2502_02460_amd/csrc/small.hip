@@ -64,16 +64,6 @@ __host__ __device__ inline size_t lds_layout(int nmax, Lds<T>* L, char* base) {
     return off;
 }
 
-// A descriptor's pointers arrive as generic addresses; telling the compiler
-// that they point to global memory lets it use global (not flat) loads and
-// stores, which do not tie up the LDS counter that flat accesses share.
-template <typename U>
-using gptr = U __attribute__((address_space(1)))*;
-template <typename U>
-__device__ __forceinline__ gptr<U> global_ptr(void* p) {
-    return (gptr<U>)p;
-}
-
 __device__ inline double shfl_s(double v, int src) { return __shfl(v, src, WAVE); }
 __device__ inline zdouble shfl_s(zdouble v, int src) { return {__shfl(v.x, src, WAVE), __shfl(v.y, src, WAVE)}; }
 
@@ -83,7 +73,7 @@ __device__ inline zdouble shfl_s(zdouble v, int src) { return {__shfl(v.x, src, 
 // is then the same whatever launch shape runs it.  chunk holds
 // SMALL_MAX / 64 entries.
 template <int NT, typename U, typename F>
-__device__ __forceinline__ U chunked_sum(int len, F x, U* chunk) {
+__device__ U chunked_sum(int len, F x, U* chunk) {
     const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
     const int nch = (len + WAVE - 1) / WAVE;
     __syncthreads();
@@ -107,7 +97,7 @@ __device__ __forceinline__ U chunked_sum(int len, F x, U* chunk) {
 // registers.  Returns 0 or the 1-based order of the first non-positive minor.
 // ---------------------------------------------------------------------------
 template <typename T, int NT>
-__device__ __forceinline__ int chol_small(gptr<T> S, long lds, int n, T (*dblk)[RB + 1], int* ctl) {
+__device__ int chol_small(T* S, long lds, int n, T (*dblk)[RB + 1], int* ctl) {
     const int tid = threadIdx.x;
     for (int J = 0; J < n; J += RB) {
         const int nb = min(RB, n - J);
@@ -192,7 +182,7 @@ __device__ __forceinline__ int chol_small(gptr<T> S, long lds, int n, T (*dblk)[
 // Y U = B row by row, in place (B n x n); U upper from S, read through
 // U[l, c] = conj(L[c, l]) so that the RB entries a block needs are adjacent.
 template <typename T, int NT>
-__device__ __forceinline__ void row_solve(gptr<T> B, long ldb, gptr<const T> S, long lds, int n) {
+__device__ void row_solve(T* B, long ldb, const T* S, long lds, int n) {
     for (int r = threadIdx.x; r < n; r += NT) {
         for (int J = 0; J < n; J += RB) {
             const int nb = min(RB, n - J);
@@ -231,7 +221,7 @@ __device__ __forceinline__ void row_solve(gptr<T> B, long ldb, gptr<const T> S, 
 // j of A; d, e (= beta) and tau stay in LDS.
 // ---------------------------------------------------------------------------
 template <typename T, int NT>
-__device__ __forceinline__ void tridiag_small(gptr<T> A, long lda, int n, Lds<T>& L, T* red, double* redd) {
+__device__ void tridiag_small(T* A, long lda, int n, Lds<T>& L, T* red, double* redd) {
     const int tid = threadIdx.x;
     T *v = L.v, *w = L.w, *v2 = L.v2, *y2 = L.y2;
     bool pending = false;
@@ -339,8 +329,7 @@ __device__ inline double pyth(double f, double g) {
 }
 
 template <int NT>
-__device__ __forceinline__ bool ql_small(int n, double* d, double* e, double* rc, double* rs, gptr<double> Z,
-                                         int* ctl) {
+__device__ bool ql_small(int n, double* d, double* e, double* rc, double* rs, double* Z, int* ctl) {
     const int tid = threadIdx.x;
     for (long x = tid; x < (long)n * n; x += NT) {
         const int c = (int)(x / n), r = (int)(x - (long)c * n);
@@ -469,7 +458,7 @@ __device__ __forceinline__ bool ql_small(int n, double* d, double* e, double* rc
 // orthogonalisation or its residual ||T z - lambda z|| exceeds 1e-10 ||T||
 // (QL's vectors are orthogonal whatever the gaps, at O(n^3) cost).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int sturm_count(int n, const double* d, const double* e, double x, double pivmin) {
+__device__ inline int sturm_count(int n, const double* d, const double* e, double x, double pivmin) {
     double q = d[0] - x;
     if (fabs(q) < pivmin) q = -pivmin;
     int cnt = q < 0.0;
@@ -482,8 +471,8 @@ __device__ __forceinline__ int sturm_count(int n, const double* d, const double*
 }
 
 template <int NT>
-__device__ __forceinline__ bool bisect_twist_small(int n, int nev, const double* d, const double* e, double* w, double* dots,
-                                   gptr<double> Z, double* redd, int* ctl) {
+__device__ bool bisect_twist_small(int n, int nev, const double* d, const double* e, double* w, double* dots,
+                                   double* Z, double* redd, int* ctl) {
     const int tid = threadIdx.x;
     // Gershgorin interval and the pivot floor (every lane the same values)
     double glo = d[0], ghi = d[0], emax2 = 0.0;
@@ -518,7 +507,7 @@ __device__ __forceinline__ bool bisect_twist_small(int n, int nev, const double*
     auto guard = [&](double x) { return fabs(x) < tiny ? (x < 0.0 ? -tiny : tiny) : x; };
     for (int i = tid; i < nev; i += NT) {
         const double lam = w[i];
-        gptr<double> zc = Z + i;  // entry r at zc[r n]
+        double* zc = Z + i;  // entry r at zc[r n]
         // forward pivots D+ into the vector's column
         double dp = d[0] - lam;
         for (int r = 0; r + 1 < n; ++r) {
@@ -633,13 +622,12 @@ __device__ __forceinline__ bool bisect_twist_small(int n, int nev, const double*
 // U x = y by back substitution with columns of U (adjacent in memory).
 // ---------------------------------------------------------------------------
 template <typename T, int NT>
-__device__ __forceinline__ void back_small(const SmallDesc& D, gptr<const T> A, gptr<const T> S, gptr<const double> Z,
-                                           const Lds<T>& L,
+__device__ void back_small(const SmallDesc& D, const T* A, const T* S, const double* Z, const Lds<T>& L,
                            bool rowmajor) {
     const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
     const int n = D.n;
     const long lda = D.ldh, lds = D.lds, ldc = D.ldc;
-    gptr<T> C = global_ptr<T>(D.C);
+    T* C = reinterpret_cast<T*>(D.C);
     for (int c = wv; c < D.nev; c += NT / WAVE) {
         T y[QMAX];
         const int zc = min(max(L.perm[c], 0), n - 1);
@@ -657,7 +645,7 @@ __device__ __forceinline__ void back_small(const SmallDesc& D, gptr<const T> A, 
 #pragma unroll
             for (int q = 0; q < QMAX; ++q) {
                 const int r = lane + q * WAVE;
-                vq[q] = r == o ? from_real<T>(1.0) : (r > o && r < n ? T(A[IDX(r, j, lda)]) : zero_of<T>());
+                vq[q] = r == o ? from_real<T>(1.0) : (r > o && r < n ? A[IDX(r, j, lda)] : zero_of<T>());
                 dot += conjg(vq[q]) * y[q];
             }
             const T wgt = tau * wave_sum(dot);
@@ -687,14 +675,12 @@ __device__ __forceinline__ void back_small(const SmallDesc& D, gptr<const T> A, 
 }
 
 template <typename T, int NT>
-__device__ __forceinline__ void solve_one(const SmallDesc& D, gptr<double> Z, Lds<T>& L, T (*dblk)[RB + 1], T* red, double* redd,
+__device__ void solve_one(const SmallDesc& D, double* Z, Lds<T>& L, T (*dblk)[RB + 1], T* red, double* redd,
                           int* ctl) {
     const int tid = threadIdx.x;
     const int n = D.n;
-    gptr<T> H = global_ptr<T>(D.H);
-    gptr<T> S = global_ptr<T>(D.S);
-    gptr<double> eval = global_ptr<double>(D.eval);
-    gptr<int> info = global_ptr<int>(D.info);
+    T* H = reinterpret_cast<T*>(D.H);
+    T* S = reinterpret_cast<T*>(D.S);
     const long ldh = D.ldh, lds = D.lds;
     SMALL_MARK_INIT();
     const bool factor = !D.factored;
@@ -711,14 +697,14 @@ __device__ __forceinline__ void solve_one(const SmallDesc& D, gptr<double> Z, Ld
         }
     }
     if (__syncthreads_or(bad)) {
-        if (tid == 0) *info = GEVD_E_NONFINITE;
+        if (tid == 0) *D.info = GEVD_E_NONFINITE;
         return;
     }
     SMALL_MARK(0);
     if (factor) {  // otherwise S keeps U and U^H from an earlier solve (fixed overlap)
         const int minor = chol_small<T, NT>(S, lds, n, dblk, ctl);
         if (minor) {
-            if (tid == 0) *info = minor;
+            if (tid == 0) *D.info = minor;
             return;
         }
     }
@@ -763,11 +749,11 @@ __device__ __forceinline__ void solve_one(const SmallDesc& D, gptr<double> Z, Ld
     for (int i = tid; i < n; i += NT) L.perm[i] = i;
     const bool fast = bisect_twist_small<NT>(n, D.nev, L.d, L.e, L.rc, L.rs, Z, redd, ctl);
     if (fast) {
-        for (int i = tid; i < n; i += NT) eval[i] = L.rc[i];
+        for (int i = tid; i < n; i += NT) D.eval[i] = L.rc[i];
     } else {
         // implicit QL with every vector (d and e are still T's)
         if (!ql_small<NT>(n, L.d, L.e, L.rc, L.rs, Z, ctl)) {
-            if (tid == 0) *info = GEVD_E_NOCONV;
+            if (tid == 0) *D.info = GEVD_E_NOCONV;
             return;
         }
         // ascending order by rank (ties broken by index)
@@ -781,7 +767,7 @@ __device__ __forceinline__ void solve_one(const SmallDesc& D, gptr<double> Z, Ld
             L.perm[rank] = i;
         }
         __syncthreads();
-        for (int i = tid; i < n; i += NT) eval[i] = L.d[L.perm[i]];
+        for (int i = tid; i < n; i += NT) D.eval[i] = L.d[L.perm[i]];
     }
     SMALL_MARK(5);
     __syncthreads();
@@ -789,7 +775,7 @@ __device__ __forceinline__ void solve_one(const SmallDesc& D, gptr<double> Z, Ld
     back_small<T, NT>(D, H, S, Z, L, fast);
     __syncthreads();
     SMALL_MARK(7);
-    if (tid == 0) *info = 0;
+    if (tid == 0) *D.info = 0;
 }
 
 template <typename T, int NT>
@@ -803,7 +789,7 @@ __global__ __launch_bounds__(NT) void small_solve_kernel(const SmallDesc* desc, 
     __shared__ int prob;
     Lds<T> L;
     lds_layout<T>(nmax, &L, dyn);
-    gptr<double> Z = (gptr<double>)(zws + (size_t)blockIdx.x * zslot);
+    double* Z = zws + (size_t)blockIdx.x * zslot;
     for (;;) {
         if (threadIdx.x == 0) prob = atomicAdd(counter, 1);
         __syncthreads();
