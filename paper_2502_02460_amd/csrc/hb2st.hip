@@ -630,13 +630,15 @@ __global__ __launch_bounds__(512) void back_chase_kernel(int n, int b, int nsw, 
     constexpr int NB1 = NBS / 16;                 // 16-row blocks of W = V^H Z
     constexpr int PA = NWV / NB1;                 // parts of W's inner dimension
     constexpr int KA = ((15 + MAXB + 3) / 4 + PA - 1) / PA;  // k-steps per part
-    constexpr int VR = NBS + MAXB + 4;            // dense V row (r index), = 4 mod 32
-    constexpr int TR = NBS + 4;
+    constexpr int VR = NBS + MAXB + 5;            // dense V row (r index), odd
+    constexpr int TR = NBS + 5;                   // odd
     constexpr int KS = NBS / 4;                   // k-steps over the group's reflectors
     constexpr int KP = KS / 2;                    // k-steps per part of T W
     constexpr int NRB = (NBS + MAXB - 1 + 15) / 16;
     static_assert(NRB <= NWV && 2 * NB1 <= NWV, "wave split");
-    static_assert(VR % 32 == 4 && TR % 32 == 4, "bank padding");
+    // odd row pitches: the 16 lanes of an MFMA operand read (16 rows, one
+    // column) fall on 16 distinct bank pairs
+    static_assert(VR % 2 == 1 && TR % 2 == 1, "bank padding");
     static_assert(16 * (NB1 - 1) + 4 * PA * KA <= VR, "dense V rows");
     __shared__ double vd[NC][NBS][VR];
     __shared__ double tm[NC][NBS][TR];
