@@ -201,6 +201,10 @@ __global__ __launch_bounds__(64) void hb2st_kernel(int n, int b, T* Bw, long ldw
             // the lower triangle of D = B[r0.., r0..].  Lanes 0-31 and 32-63
             // take alternate columns of rows lane % 32 (b <= 32 here): all
             // loads are issued before the first one is used.
+            // E's columns from pr0 (t > 0), D's from r0: single buffer
+            // accesses at system scope, unowned elements masked by offset
+            const auto rE = band_rsrc(Bw + IDX(0, max(pr0, 0), ldw));
+            const auto rD = band_rsrc(Bw + IDX(0, r0, ldw));
             {
                 constexpr int HB = 32;
                 const int i = lane % HB, jh = lane / HB;
@@ -208,8 +212,10 @@ __global__ __launch_bounds__(64) void hb2st_kernel(int n, int b, T* Bw, long ldw
 #pragma unroll
                 for (int k = 0; k < HB / 2; ++k) {
                     const int j = jh + 2 * k;
-                    te[k] = (t > 0 && i < L && j < b) ? sys_load(&Bw[IDX(b + i - j, pr0 + j, ldw)]) : zero_of<T>();
-                    td[k] = (i < L && j <= i) ? sys_load(&Bw[IDX(i - j, r0 + j, ldw)]) : zero_of<T>();
+                    te[k] = band_load((T*)nullptr, rE,
+                                      (t > 0 && i < L && j < b) ? (unsigned)(IDX(b + i - j, j, ldw) * sizeof(T)) : BOOB);
+                    td[k] = band_load((T*)nullptr, rD,
+                                      (i < L && j <= i) ? (unsigned)(IDX(i - j, j, ldw) * sizeof(T)) : BOOB);
                 }
 #pragma unroll
                 for (int k = 0; k < HB / 2; ++k) {
@@ -248,12 +254,15 @@ __global__ __launch_bounds__(64) void hb2st_kernel(int n, int b, T* Bw, long ldw
                     }
                     __syncthreads();
                     const T ctau = conjg(sc[0]);
-                    if (lane < L) {
-                        const int i = lane;
+                    {
+                        // every lane runs the same loop (rows >= L are masked
+                        // by offset and read row 0 of the LDS block)
+                        const int i = lane < L ? lane : 0;
                         const T cv = ctau * v[i];
-                        for (int j = 1; j < b; ++j)
-                            sys_store(&Bw[IDX(b + i - j, pr0 + j, ldw)], EL_(i, j) - cv * y[j]);
-                        sys_store(&Bw[IDX(b + i, pr0, ldw)], (i == 0) ? sc[1] : zero_of<T>());
+                        for (int j = 0; j < b; ++j) {
+                            const T x = (j == 0) ? ((lane == 0) ? sc[1] : zero_of<T>()) : EL_(i, j) - cv * y[j];
+                            band_store(x, rE, lane < L ? (unsigned)(IDX(b + lane - j, j, ldw) * sizeof(T)) : BOOB);
+                        }
                     }
                 } else {
                     if (lane == 0) {
@@ -278,12 +287,13 @@ __global__ __launch_bounds__(64) void hb2st_kernel(int n, int b, T* Bw, long ldw
                 const T coef = from_real<T>(-0.5) * tau * yv;  // w = y - 1/2 tau (y^H v) v
                 if (lane < L) y[lane] = y[lane] + coef * v[lane];
                 __syncthreads();
-                if (lane < L) {
-                    const int i = lane;
-                    for (int j = 0; j <= i; ++j) {
+                {
+                    const int i = lane < L ? lane : 0;
+                    for (int j = 0; j < b; ++j) {
                         T x = DL_(i, j) - v[i] * conjg(y[j]) - y[i] * conjg(v[j]);
                         if (i == j) x = from_real<T>(realp(x));
-                        sys_store(&Bw[IDX(i - j, r0 + j, ldw)], x);
+                        band_store(x, rD,
+                                   (lane < L && j <= lane) ? (unsigned)(IDX(lane - j, j, ldw) * sizeof(T)) : BOOB);
                     }
                 }
             }
