@@ -257,13 +257,23 @@ int eigh_run(const StageCtx& c, int n, int nev, T* A, long lda, double* eval, T*
     }
     c.phase(GEVD_PH_TRIDIAG);
     if ((rc = hb2st<T>(c, n, w.Bw, w.ldw, w.R2, w.d, w.e, w.sync_area))) return rc;
+    // the stage-2 T factors on the second stream, beside the tridiagonal
+    // solve (which leaves the device idle at its host synchronisations)
+    const bool tf_aux = c.aux != nullptr && c.fork != nullptr && c.join != nullptr;
+    if (tf_aux) {
+        GEVD_HIP(hipEventRecord(c.fork, c.st));
+        GEVD_HIP(hipStreamWaitEvent(c.aux, c.fork, 0));
+        if ((rc = back_chase_tfactor<T>(w.R2, c.aux))) return rc;
+        GEVD_HIP(hipEventRecord(c.join, c.aux));
+    }
     c.phase(GEVD_PH_SOLVE);
     if ((rc = stedc_run(c, n, nev, w.d, w.e, eval, w.Zr, n, w.dc_ws))) return rc;
     c.phase(GEVD_PH_BACK2);
     if (is_cplx<T>::value) rc = real_to_scalar_z(c.st, n, nev, w.Zr, n, reinterpret_cast<zdouble*>(Z), ldz);
     else rc = real_to_scalar_d(c.st, n, nev, w.Zr, n, reinterpret_cast<double*>(Z), ldz);
     if (rc) return rc;
-    if ((rc = back_chase<T>(c, w.R2, nev, Z, ldz))) return rc;
+    if (tf_aux) GEVD_HIP(hipStreamWaitEvent(c.st, c.join, 0));
+    if ((rc = back_chase<T>(c, w.R2, nev, Z, ldz, tf_aux))) return rc;
     c.phase(GEVD_PH_BACK1);
     {
         Fp32Gemm f32(c.prec != 0);

@@ -907,16 +907,24 @@ int hb2st(const StageCtx& c, int n, T* Bw, long ldw, ChaseRefl<T>& R, double* d,
 }
 
 template <typename T>
-int back_chase(const StageCtx& c, const ChaseRefl<T>& R, int nev, T* Z, long ldz) {
+int back_chase_tfactor(const ChaseRefl<T>& R, hipStream_t st) {
+    if (R.nsw <= 0) return 0;
+    constexpr int NBS = chase_group<T>();
+    if (R.nbs != NBS || R.Tg == nullptr || R.b > MAXB) return GEVD_E_STATE;
+    KProbe probe(st, GEVD_K_OTHER, 0.0);
+    hipLaunchKernelGGL((chase_tfactor_kernel<T, NBS>), dim3(R.nblk, R.tmax), dim3(256), 0, st, R.n, R.b, R.nsw,
+                       R.nblk, (const T*)R.V2, (const T*)R.tau2, R.Tg);
+    GEVD_LAUNCH_CHECK();
+    return 0;
+}
+
+template <typename T>
+int back_chase(const StageCtx& c, const ChaseRefl<T>& R, int nev, T* Z, long ldz, bool tfactored) {
     if (R.nsw <= 0 || nev <= 0) return 0;
     constexpr int NBS = chase_group<T>();
     if (R.nbs != NBS || R.Tg == nullptr || R.b > MAXB) return GEVD_E_STATE;
-    {
-        KProbe probe(c.st, GEVD_K_OTHER, 0.0);
-        hipLaunchKernelGGL((chase_tfactor_kernel<T, NBS>), dim3(R.nblk, R.tmax), dim3(256), 0, c.st, R.n, R.b,
-                           R.nsw, R.nblk, (const T*)R.V2, (const T*)R.tau2, R.Tg);
-        GEVD_LAUNCH_CHECK();
-    }
+    int rc;
+    if (!tfactored && (rc = back_chase_tfactor<T>(R, c.st))) return rc;
     const int grid = (nev + 15) / 16;
     // algorithmic work: every reflector applied to every column, 4 L nev
     // real flops each (x4 complex): about 2 n^2 nev in total
@@ -929,7 +937,8 @@ int back_chase(const StageCtx& c, const ChaseRefl<T>& R, int nev, T* Z, long ldz
 
 #define INST(T)                                                                              \
     template int hb2st<T>(const StageCtx&, int, T*, long, ChaseRefl<T>&, double*, double*, int*); \
-    template int back_chase<T>(const StageCtx&, const ChaseRefl<T>&, int, T*, long);
+    template int back_chase_tfactor<T>(const ChaseRefl<T>&, hipStream_t);                          \
+    template int back_chase<T>(const StageCtx&, const ChaseRefl<T>&, int, T*, long, bool);
 INST(double)
 INST(zdouble)
 #undef INST

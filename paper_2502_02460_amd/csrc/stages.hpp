@@ -94,8 +94,13 @@ template <typename T>
 int he2hb(const StageCtx& c, int n, T* A, long lda, BandRefl<T>& R, T* Bd, long ldb, T* work);
 template <typename T>
 int hb2st(const StageCtx& c, int n, T* Bw, long ldw, ChaseRefl<T>& R, double* d, double* e, int* sync_area);
+// The compact-WY T factors of all stage-2 reflector groups, on stream st
+// (they depend only on the reflectors, so they may run beside the
+// tridiagonal solve); back_chase forms them itself unless tfactored.
 template <typename T>
-int back_chase(const StageCtx& c, const ChaseRefl<T>& R, int nev, T* Z, long ldz);
+int back_chase_tfactor(const ChaseRefl<T>& R, hipStream_t st);
+template <typename T>
+int back_chase(const StageCtx& c, const ChaseRefl<T>& R, int nev, T* Z, long ldz, bool tfactored = false);
 template <typename T>
 int back_band(const StageCtx& c, const BandRefl<T>& R, int nev, T* Z, long ldz, T* work);
 template <typename T>
