@@ -129,24 +129,15 @@ struct PanelLease {
 };
 
 // The second stream of overlapped stages (default priority, ordered against
-// the handle's stream by events only); left null if it cannot be made.
-// Its work may not use the last few CUs, which stay free for the latency-
-// bound kernels running on the handle's stream at the same time.
+// the handle's stream by events only); left null if it cannot be made.  It
+// may use every CU: reserving the last 16 or 32 CUs for the latency-bound
+// panel kernels running beside it made the full -> band stage 4 % slower
+// on gfx950 (the trailing updates lost more than the panels gained).
 void attach_aux(gevd_ctx* h, StageCtx& sc) {
     sc.panel_persist = h->persist_now;
     sc.stages = h->stages;
     if (!h->aux) {
-        int ncu = 0;
-        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h->device) != hipSuccess) ncu = 0;
-        constexpr int RESERVE = 16;
-        bool made = false;
-        if (ncu > 4 * RESERVE && ncu <= 32 * 16) {
-            uint32_t mask[16] = {};
-            for (int cu = 0; cu < ncu - RESERVE; ++cu) mask[cu / 32] |= 1u << (cu % 32);
-            made = hipExtStreamCreateWithCUMask(&h->aux, (uint32_t)((ncu + 31) / 32), mask) == hipSuccess;
-        }
-        if (!made) (void)hipGetLastError();
-        if ((!made && hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking) != hipSuccess) ||
+        if (hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking) != hipSuccess ||
             hipEventCreateWithFlags(&h->aux_fork, hipEventDisableTiming) != hipSuccess ||
             hipEventCreateWithFlags(&h->aux_join, hipEventDisableTiming) != hipSuccess) {
             (void)hipGetLastError();
