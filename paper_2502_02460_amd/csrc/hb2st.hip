@@ -96,10 +96,11 @@ __device__ inline void householder(T alpha, double a2, T* tau, double* beta, T* 
 
 // Sum over the 64 lanes of each of C values per lane, C a power of two <= 16:
 // exchanges that halve the values at each step (lane bit 2 log2(C)+1 .. 2
-// picks the half), then two plain exchanges; on return v[0] of lane l holds
-// the sum of value (l >> 2) % C.  Fixed order: the same bits on every run.
+// picks the half), then plain exchanges over the remaining lane bits; on
+// return v[0] of lane l holds the sum of value (l >> 2) % C.  Fixed order:
+// the same bits on every run.
 template <typename T, int C>
-__device__ inline void lane_fold(T* v, int lane) {
+__device__ inline void lane_halve(T* v, int lane) {
     if constexpr (C > 1) {
         constexpr int H = C / 2;
         const bool up = (lane & (4 * H)) != 0;
@@ -109,11 +110,16 @@ __device__ inline void lane_fold(T* v, int lane) {
             const T send = up ? v[i] : v[i + H];
             v[i] = keep + shfl_xor_s(send, 4 * H);
         }
-        lane_fold<T, H>(v, lane);
-    } else {
-        v[0] += shfl_xor_s(v[0], 1);
-        v[0] += shfl_xor_s(v[0], 2);
+        lane_halve<T, H>(v, lane);
     }
+}
+template <typename T, int C>
+__device__ inline void lane_fold(T* v, int lane) {
+    lane_halve<T, C>(v, lane);
+    v[0] += shfl_xor_s(v[0], 1);
+    v[0] += shfl_xor_s(v[0], 2);
+#pragma unroll
+    for (int m = 4 * C; m < WAVE; m *= 2) v[0] += shfl_xor_s(v[0], m);
 }
 
 // Householder reflector for x[0..L-1] (LDS, overwritten by v with v[0] = 1):
@@ -316,11 +322,15 @@ __global__ __launch_bounds__(64) void hb2st_kernel(int n, int b, T* Bw, long ldw
 #undef DL_
 }
 
-// Four-wave variant for wider bands (b > 32), where the single wave's row
+// Workgroup variant for wider bands (b > 32), where the single wave's row
 // loops dominate a task: row i of the blocks is handled by lane i of every
-// wave, the four waves split the inner index of each block product into
-// quarters and add their partial sums in a fixed order (deterministic).
-constexpr int CW = 4;  // waves per workgroup
+// wave, the CW waves split the inner index of each block product (wave w
+// takes columns w, w + CW, ...) and add their partial sums in a fixed order
+// (deterministic).  Sixteen waves (the largest workgroup) measured fastest:
+// a task's arithmetic is short chains per lane, so more waves shorten it
+// (complex n = 16384, b = 64: 340 ms with four waves, 282 with eight, 265 with
+// sixteen).
+constexpr int CW = 16;  // waves per workgroup
 
 template <typename T>
 __global__ __launch_bounds__(64 * CW) void hb2st_kernel_wg(int n, int b, T* Bw, long ldw, T* V2, T* tau2, int nsw,
@@ -331,6 +341,7 @@ __global__ __launch_bounds__(64 * CW) void hb2st_kernel_wg(int n, int b, T* Bw, 
     const int ldl = b + 1;
     __shared__ T v[MAXB], vp[MAXB], y[MAXB];
     __shared__ T part[CW][MAXB];
+    __shared__ T rsum[MAXB];
     __shared__ T sc[4];
     __shared__ T ptau;
     __shared__ int sw_s, stop;
@@ -419,21 +430,21 @@ __global__ __launch_bounds__(64 * CW) void hb2st_kernel_wg(int n, int b, T* Bw, 
                     part[wv][lane] = acc;
                 }
                 __syncthreads();
-                {
+                // wave 0 adds the partial row sums, updates its columns and
+                // forms the next reflector from column 0 (its first register
+                // column: norm by a wave sum, alpha by a lane broadcast); the
+                // other waves update their columns after the barrier
+                if (wv == 0) {
                     T acc = part[0][lane];
 #pragma unroll
                     for (int w = 1; w < CW; ++w) acc += part[w][lane];
                     const T pa = ptau * acc;
+                    rsum[lane] = pa;
 #pragma unroll
-                    for (int k = 0; k < KW; ++k) te[k] -= pa * conjg(vp[wv + CW * k]);
-                }
-                if (wv == 0) v[lane] = (lane < L) ? te[0] : zero_of<T>();
-                if (L >= 2) {
-                    // the next reflector from column 0 (wave 0's first
-                    // register column): norm by a wave sum, alpha by a lane
-                    // broadcast, no LDS round trip
-                    if (wv == 0) {
-                        const T x = (lane < L) ? te[0] : zero_of<T>();
+                    for (int k = 0; k < KW; ++k) te[k] -= pa * conjg(vp[CW * k]);
+                    const T x = (lane < L) ? te[0] : zero_of<T>();
+                    v[lane] = x;
+                    if (L >= 2) {
                         const double a2 = wave_sum((lane >= 1 && lane < L) ? abs2(x) : 0.0);
                         T tau, scale;
                         double beta;
@@ -445,7 +456,14 @@ __global__ __launch_bounds__(64 * CW) void hb2st_kernel_wg(int n, int b, T* Bw, 
                             sc[2] = scale;
                         }
                     }
-                    __syncthreads();
+                }
+                __syncthreads();
+                if (wv != 0) {
+                    const T pa = rsum[lane];
+#pragma unroll
+                    for (int k = 0; k < KW; ++k) te[k] -= pa * conjg(vp[wv + CW * k]);
+                }
+                if (L >= 2) {
                     // y_j = v^H E[:, j] for this wave's columns, summed over the
                     // lanes (rows) by halving exchanges; lanes 4k .. 4k+3 end
                     // with y of column wv + CW k
@@ -465,7 +483,6 @@ __global__ __launch_bounds__(64 * CW) void hb2st_kernel_wg(int n, int b, T* Bw, 
                                    (lane < L && j < b) ? (unsigned)(IDX(b + lane - j, j, ldw) * sizeof(T)) : BOOB);
                     }
                 } else {
-                    __syncthreads();
                     if (tid == 0) {
                         v[0] = from_real<T>(1.0);
                         sc[0] = zero_of<T>();
@@ -519,15 +536,15 @@ __global__ __launch_bounds__(64 * CW) void hb2st_kernel_wg(int n, int b, T* Bw, 
                     }
                 }
             }
-            const size_t slot = (size_t)t * nsw + sw;
-            if (tid < b) V2[slot * b + tid] = (tid < L) ? v[tid] : zero_of<T>();
-            if (tid == 0) tau2[slot] = tau;
-            __syncthreads();
             if (tid < MAXB) vp[tid] = (tid < L) ? v[tid] : zero_of<T>();
             if (tid == 0) ptau = tau;
             __builtin_amdgcn_s_waitcnt(0);
             __syncthreads();
             if (tid == 0) __hip_atomic_store(&progress[sw], t + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            // the reflector itself is read only after the kernel (back-transformation)
+            const size_t slot = (size_t)t * nsw + sw;
+            if (tid < b) V2[slot * b + tid] = (tid < L) ? v[tid] : zero_of<T>();
+            if (tid == 0) tau2[slot] = tau;
         }
     }
 #undef EL_
@@ -887,7 +904,7 @@ int hb2st(const StageCtx& c, int n, T* Bw, long ldw, ChaseRefl<T>& R, double* d,
         int* counter = sync_area + R.nsw + 1;
         const int grid = std::min(R.nsw, 1024);
         const size_t lds = (size_t)2 * b * (b + 1) * sizeof(T);
-        const bool wide = b > 32;  // four waves per sweep pay off only for wider bands
+        const bool wide = b > 32;  // a workgroup per sweep pays off only for wider bands
         GEVD_HIP(hipFuncSetAttribute(wide ? reinterpret_cast<const void*>(&hb2st_kernel_wg<T>)
                                           : reinterpret_cast<const void*>(&hb2st_kernel<T>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));

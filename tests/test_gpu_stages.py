@@ -221,7 +221,7 @@ def test_solve_parity(solver, n, frac, smin, cplx):
     assert orth < max(1e-11, 10 * orth_ref)
 
 
-# ------------------------------------------- wide bands (four-wave bulge chasing)
+# ------------------------------------ wide bands (workgroup bulge chasing, b > 32)
 @pytest.mark.parametrize("cplx", [False, True])
 @pytest.mark.parametrize("n,b", cases.WIDE_BAND)
 def test_wide_band_tridiagonal_and_solve(gpu_lib, n, b, cplx):
