@@ -322,14 +322,14 @@ __global__ __launch_bounds__(64) void hb2st_kernel(int n, int b, T* Bw, long ldw
 #undef DL_
 }
 
-// Workgroup variant for wider bands (b > 32), where the single wave's row
-// loops dominate a task: row i of the blocks is handled by lane i of every
+// Workgroup variant (b > 8), where the single wave's row loops would
+// dominate a task: row i of the blocks is handled by lane i of every
 // wave, the CW waves split the inner index of each block product (wave w
 // takes columns w, w + CW, ...) and add their partial sums in a fixed order
 // (deterministic).  Sixteen waves (the largest workgroup) measured fastest:
 // a task's arithmetic is short chains per lane, so more waves shorten it
 // (complex n = 16384, b = 64: 340 ms with four waves, 282 with eight, 265 with
-// sixteen).
+// sixteen; real n = 4096, b = 32: 106 ms with one wave, 46 with sixteen).
 constexpr int CW = 16;  // waves per workgroup
 
 template <typename T>
@@ -904,7 +904,7 @@ int hb2st(const StageCtx& c, int n, T* Bw, long ldw, ChaseRefl<T>& R, double* d,
         int* counter = sync_area + R.nsw + 1;
         const int grid = std::min(R.nsw, 1024);
         const size_t lds = (size_t)2 * b * (b + 1) * sizeof(T);
-        const bool wide = b > 32;  // a workgroup per sweep pays off only for wider bands
+        const bool wide = b > 8;  // a workgroup per sweep pays off except for the narrowest bands
         GEVD_HIP(hipFuncSetAttribute(wide ? reinterpret_cast<const void*>(&hb2st_kernel_wg<T>)
                                           : reinterpret_cast<const void*>(&hb2st_kernel<T>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));

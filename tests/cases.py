@@ -8,8 +8,9 @@ from tests import floors
 
 # test_gpu_stages.test_solve_parity: (n, wanted fraction, sigma_min), seed 800 + n
 SOLVE = [(1, 1.0, 1e-3), (3, 1.0, 1e-3), (256, 1.0, 1e-3), (300, 0.3, 1e-6), (513, 0.25, 1e-6)]
-# test_gpu_stages.test_wide_band_tridiagonal_and_solve: (n, b), seed 1100 + n + b
-WIDE_BAND = [(129, 40), (300, 64), (700, 64), (333, 48)]
+# test_gpu_stages.test_band_width_tridiagonal_and_solve: (n, b), seed 1100 + n + b
+# (b = 8 takes the single-wave bulge-chasing kernel, the others the workgroup one)
+BANDS = [(129, 40), (300, 64), (700, 64), (333, 48), (201, 8)]
 # test_gpu_stages.test_per_column_panel_route: n, seed 1500 + n
 PER_COLUMN = [700, 1100]
 # test_gpu_gemm_tiles: forced GEMM tile per process, (n, complex), seed 2100 + n
@@ -27,7 +28,7 @@ def solve_pencil(n, frac, smin, cplx):
     return synth.pencil(n, cplx, smin, 800 + n, frac), floors.key("pencil", n, cplx, smin, 800 + n, frac)
 
 
-def wide_band_pencil(n, b, cplx):
+def band_pencil(n, b, cplx):
     return (synth.pencil(n, cplx, 1e-6, 1100 + n + b, 0.3),
             floors.key("pencil", n, cplx, 1e-6, 1100 + n + b, 0.3))
 
@@ -73,8 +74,8 @@ def all_cases(include_large: bool = True):
     for cplx in (False, True):
         for n, frac, smin in SOLVE:
             add(*solve_pencil(n, frac, smin, cplx))
-        for n, b in WIDE_BAND:
-            add(*wide_band_pencil(n, b, cplx))
+        for n, b in BANDS:
+            add(*band_pencil(n, b, cplx))
         for n in PER_COLUMN:
             add(*per_column_pencil(n, cplx))
         for n in RESIDENT:

@@ -221,13 +221,13 @@ def test_solve_parity(solver, n, frac, smin, cplx):
     assert orth < max(1e-11, 10 * orth_ref)
 
 
-# ------------------------------------ wide bands (workgroup bulge chasing, b > 32)
+# ------------------------- band widths (single-wave and workgroup bulge chasing)
 @pytest.mark.parametrize("cplx", [False, True])
-@pytest.mark.parametrize("n,b", cases.WIDE_BAND)
-def test_wide_band_tridiagonal_and_solve(gpu_lib, n, b, cplx):
+@pytest.mark.parametrize("n,b", cases.BANDS)
+def test_band_width_tridiagonal_and_solve(gpu_lib, n, b, cplx):
     s = gpu_lib.Solver(band=b)
     assert s.band_width(n, torch.complex128 if cplx else torch.float64) == b
-    p, key = cases.wide_band_pencil(n, b, cplx)
+    p, key = cases.band_pencil(n, b, cplx)
     A0 = oracle.reduce(p.H, oracle.cholesky(p.S))
     d, e = s.tridiagonalize(dev(A0))
     d, e = host(d), host(e)
@@ -238,7 +238,7 @@ def test_wide_band_tridiagonal_and_solve(gpu_lib, n, b, cplx):
     w_ref, C_ref, _ = oracle.gevd(p.H, p.S, p.k)
     ws, C = s.solve(dev(p.H), dev(p.S), p.k)
     ws, C = host(ws), host(C)
-    floors.check_eigs(ws, w_ref, p.k, floors.stored(key), f"wide band n={n} b={b} cplx={cplx}:")
+    floors.check_eigs(ws, w_ref, p.k, floors.stored(key), f"band n={n} b={b} cplx={cplx}:")
     eta = backward_errors(p.H, p.S, ws[: p.k], C).max()
     orth, orth_ref = s_orthonormality(p.S, C), s_orthonormality(p.S, C_ref)
     log(f"  tridiag eig {err_t:.2e}; eta {eta:.2e} orth {orth:.2e} (oracle {orth_ref:.2e})")
