@@ -306,11 +306,23 @@ __global__ void merge_rotate_kernel(int n, double* Z0, double* Z1, const MergeDe
     }
 }
 
+// Each root is found by SG consecutive lanes: lane q of the group takes the
+// terms i = q, q + SG, ... of every sum over the poles, and the group adds
+// its partial sums by exchanges (xor butterfly: every lane ends with the same
+// bits, so the group follows one control path).
+constexpr int SG = 8;
+__device__ inline double group_sum(double v) {
+#pragma unroll
+    for (int m = 1; m < SG; m *= 2) v += __shfl_xor(v, m, WAVE);
+    return v;
+}
+
 // f(origin + tau) for the secular equation, differences taken from the origin.
-__device__ inline double secular(const double* delta, const double* zc, int kn, double rho, double dorg, double tau) {
-    double f = 1.0;
-    for (int i = 0; i < kn; ++i) f += rho * zc[i] * zc[i] / ((delta[i] - dorg) - tau);
-    return f;
+__device__ inline double secular(const double* delta, const double* zc, int kn, double rho, double dorg, double tau,
+                                 int q) {
+    double f = 0.0;
+    for (int i = q; i < kn; i += SG) f += rho * zc[i] * zc[i] / ((delta[i] - dorg) - tau);
+    return 1.0 + group_sum(f);
 }
 
 // Root j of 1 + rho sum_i z_i^2/(delta_i - lam), lam = delta[o] + tau with o
@@ -320,12 +332,15 @@ __device__ inline double secular(const double* delta, const double* zc, int kn, 
 // the last root one pole), and steps to the model's root in the interval.
 // The sign of f keeps a bracket; a model step that leaves it is replaced by
 // bisection, so convergence never depends on the model.
-__global__ void merge_secular_kernel(const double* e, const MergeDesc* md, const double* delta_all,
-                                     const double* zc_all, int* org, double* tauv, double* lam) {
+constexpr int SECT = 128;  // threads per workgroup (SECT / SG roots)
+__global__ __launch_bounds__(SECT) void merge_secular_kernel(const double* e, const MergeDesc* md,
+                                                             const double* delta_all, const double* zc_all, int* org,
+                                                             double* tauv, double* lam) {
     const MergeDesc M = md[blockIdx.y];
     const int kn = M.knd, off = M.off;
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= kn) return;
+    const int q = threadIdx.x % SG;
+    const int j = (blockIdx.x * SECT + threadIdx.x) / SG;
+    if (j >= kn) return;  // whole groups leave together
     const double rho = 2.0 * fabs(e[off + M.n1 - 1]);
     const double* delta = delta_all + off;
     const double* zc = zc_all + off;
@@ -334,7 +349,7 @@ __global__ void merge_secular_kernel(const double* e, const MergeDesc* md, const
     double lo, hi;
     if (!last) {
         const double gap = delta[j + 1] - delta[j];
-        const double fm = secular(delta, zc, kn, rho, delta[j], 0.5 * gap);
+        const double fm = secular(delta, zc, kn, rho, delta[j], 0.5 * gap, q);
         if (fm >= 0.0) {
             o = j;
             lo = 0.0;
@@ -346,30 +361,31 @@ __global__ void merge_secular_kernel(const double* e, const MergeDesc* md, const
         }
     } else {
         double zz = 0.0;
-        for (int i = 0; i < kn; ++i) zz += zc[i] * zc[i];
+        for (int i = q; i < kn; i += SG) zz += zc[i] * zc[i];
+        zz = group_sum(zz);
         o = j;
         lo = 0.0;
         hi = rho * zz;
-        for (int g = 0; g < 64 && secular(delta, zc, kn, rho, delta[o], hi) < 0.0; ++g) hi *= 2.0;
+        for (int g = 0; g < 64 && secular(delta, zc, kn, rho, delta[o], hi, q) < 0.0; ++g) hi *= 2.0;
     }
     const double dorg = delta[o];
     double tau = 0.5 * (lo + hi);
     for (int it = 0; it < 100; ++it) {
         double psi = 0.0, dpsi = 0.0, phi = 0.0, dphi = 0.0;
-        for (int i = 0; i <= j; ++i) {
+        for (int i = q; i <= j; i += SG) {
             const double r = zc[i] / ((delta[i] - dorg) - tau);
             psi += zc[i] * r;
             dpsi += r * r;
         }
-        for (int i = j + 1; i < kn; ++i) {
+        for (int i = j + 1 + q; i < kn; i += SG) {
             const double r = zc[i] / ((delta[i] - dorg) - tau);
             phi += zc[i] * r;
             dphi += r * r;
         }
-        psi *= rho;
-        dpsi *= rho;
-        phi *= rho;
-        dphi *= rho;
+        psi = rho * group_sum(psi);
+        dpsi = rho * group_sum(dpsi);
+        phi = rho * group_sum(phi);
+        dphi = rho * group_sum(dphi);
         const double f = 1.0 + psi + phi;
         if (f == 0.0) break;
         // below this the sign of the computed f is not meaningful
@@ -395,8 +411,8 @@ __global__ void merge_secular_kernel(const double* e, const MergeDesc* md, const
                     ok = false;
                     y = 0.0;
                 } else {
-                    const double q = 0.5 * (bq + copysign(sqrt(disc), bq));
-                    const double y1 = q / c, y2 = (q != 0.0) ? cq / q : y1;
+                    const double qq = 0.5 * (bq + copysign(sqrt(disc), bq));
+                    const double y1 = qq / c, y2 = (qq != 0.0) ? cq / qq : y1;
                     y = (y1 > D1 && y1 < D2) ? y1 : y2;
                 }
             }
@@ -414,9 +430,11 @@ __global__ void merge_secular_kernel(const double* e, const MergeDesc* md, const
         }
         tau = tn;
     }
-    org[off + j] = o;
-    tauv[off + j] = tau;
-    lam[off + j] = dorg + tau;
+    if (q == 0) {
+        org[off + j] = o;
+        tauv[off + j] = tau;
+        lam[off + j] = dorg + tau;
+    }
 }
 
 // z recomputed from the roots (Gu-Eisenstat), products arranged as ratios
@@ -693,7 +711,8 @@ int stedc_run(const StageCtx& c, int n, int nev, const double* d, const double* 
             const unsigned gk = (unsigned)((maxkn + 127) / 128);
             {
             KProbe kp_(st, GEVD_K_DC, 0.0);
-            hipLaunchKernelGGL(merge_secular_kernel, dim3(gk, nm), dim3(128), 0, st, e, (const MergeDesc*)w.md,
+            const unsigned gs = (unsigned)(((long long)maxkn * SG + SECT - 1) / SECT);
+            hipLaunchKernelGGL(merge_secular_kernel, dim3(gs, nm), dim3(SECT), 0, st, e, (const MergeDesc*)w.md,
                                (const double*)w.delta, (const double*)w.zc, w.org, w.tauv, w.lam);
             GEVD_LAUNCH_CHECK();
         }
