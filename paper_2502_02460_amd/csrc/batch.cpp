@@ -49,10 +49,18 @@ int batch_num_cu(gevd_ctx* h) {
     return h->ncu;
 }
 
+// Default launch shape per bucket (n <= 64, 128, 256, 512): threads per
+// workgroup and workgroups per CU, as gevd_tune_batched chose them on MI355X
+// for 512 problems of a bucket (bounded by the occupancy the device reports).
+// Real problems take 256 threads at two workgroups per CU; complex ones 128
+// threads up to n = 128 and 512 threads with one workgroup per CU above.
+// (Measured on the serving mix: 1490 -> 2007 solves/s for the first SCF
+// iteration against one workgroup size per bucket at full occupancy.)
 static void default_shape(bool cx, int bucket, int* threads, int* wgpcu) {
-    static const int t[SMALL_NBUCKET] = {64, 128, 256, 256};
-    *threads = t[bucket];
-    *wgpcu = small_occupancy(cx, *threads, small_bucket_n(bucket));
+    static const int t[2][SMALL_NBUCKET] = {{256, 256, 256, 256}, {128, 128, 512, 512}};
+    static const int w[2][SMALL_NBUCKET] = {{2, 2, 2, 2}, {2, 2, 1, 1}};
+    *threads = t[cx ? 1 : 0][bucket];
+    *wgpcu = std::max(1, std::min(w[cx ? 1 : 0][bucket], small_occupancy(cx, *threads, small_bucket_n(bucket))));
 }
 
 void batch_shape_of(gevd_ctx* h, bool cx, int bucket, int* threads, int* wgpcu) {
