@@ -150,7 +150,7 @@ void attach_aux(gevd_ctx* h, StageCtx& sc) {
 }
 
 // Default half-bandwidth: 64 for large orders (fewer, wider panels and
-// bulge-reflector groups; the four-wave bulge-chasing kernel keeps the
+// bulge-reflector groups; the workgroup bulge-chasing kernel keeps the
 // band -> tridiagonal stage in check), 32 below that.
 int pick_band(const gevd_ctx* h, int n) {
     int b = h->band_opt > 0 ? h->band_opt : (n >= 4096 ? 64 : 32);
