@@ -311,10 +311,13 @@ int gevd_reset_kernel_stats(gevd_handle h);
  * (n <= 64, 128, 256, 512); each group is one launch of a persistent fused
  * kernel whose workgroups take problems from a queue and run the whole
  * solve of gevd_solve on each one (Cholesky, the reduction by two
- * triangular solves, one-stage Householder tridiagonalisation, implicit QL,
+ * triangular solves, one-stage Householder tridiagonalisation, all
+ * eigenvalues by bisection and the wanted eigenvectors by twisted
+ * factorisations, implicit QL with all vectors as the fallback,
  * back-transformation).  Launch shapes (lanes per workgroup, workgroups
  * per CU) come from the handle's table (gevd_set_batch_shape /
- * gevd_tune_batched) or a default derived from occupancy.
+ * gevd_tune_batched) or a default table (the shapes the tuner chose on
+ * MI355X, bounded by the occupancy the device reports).
  */
 typedef struct {
     int dtype;     /* GEVD_REAL or GEVD_COMPLEX */
