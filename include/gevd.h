@@ -371,7 +371,7 @@ int gevd_batch_run_async(gevd_batch b, int *info_dev);
 int gevd_batch_destroy(gevd_batch b);
 
 /* Launch shape of the bucket holding order n: threads per workgroup (64,
- * 128, 256 or 512; 0 restores the default) and workgroups per CU. */
+ * 128, 256, 512 or 1024; 0 restores the default) and workgroups per CU. */
 int gevd_set_batch_shape(gevd_handle h, int dtype, int n, int threads, int wg_per_cu);
 int gevd_get_batch_shape(gevd_handle h, int dtype, int n, int *threads, int *wg_per_cu);
 

@@ -52,13 +52,15 @@ int batch_num_cu(gevd_ctx* h) {
 // Default launch shape per bucket (n <= 64, 128, 256, 512): threads per
 // workgroup and workgroups per CU, as gevd_tune_batched chose them on MI355X
 // for 512 problems of a bucket (bounded by the occupancy the device reports).
-// Real problems take 256 threads at two workgroups per CU; complex ones 128
-// threads up to n = 128 and 512 threads with one workgroup per CU above.
-// (Measured on the serving mix: 1490 -> 2007 solves/s for the first SCF
-// iteration against one workgroup size per bucket at full occupancy.)
+// Real problems take 256 threads at two workgroups per CU up to n = 256
+// and 1024 threads with one workgroup per CU above; complex ones 128 threads
+// up to n = 128 and 512 threads with one workgroup per CU above.  (Measured
+// on the serving mix, first SCF iteration: 1490 solves/s with one workgroup
+// size per bucket at full occupancy, 2007 with the tuned shapes up to 512
+// threads, 2330 with 1024 threads for real n > 256.)
 static void default_shape(bool cx, int bucket, int* threads, int* wgpcu) {
-    static const int t[2][SMALL_NBUCKET] = {{256, 256, 256, 256}, {128, 128, 512, 512}};
-    static const int w[2][SMALL_NBUCKET] = {{2, 2, 2, 2}, {2, 2, 1, 1}};
+    static const int t[2][SMALL_NBUCKET] = {{256, 256, 256, 1024}, {128, 128, 512, 512}};
+    static const int w[2][SMALL_NBUCKET] = {{2, 2, 2, 1}, {2, 2, 1, 1}};
     *threads = t[cx ? 1 : 0][bucket];
     *wgpcu = std::max(1, std::min(w[cx ? 1 : 0][bucket], small_occupancy(cx, *threads, small_bucket_n(bucket))));
 }
@@ -321,7 +323,8 @@ int gevd_set_batch_shape(gevd_handle h, int dtype, int n, int threads, int wg_pe
     if (!h) return -1;
     if (dtype != GEVD_REAL && dtype != GEVD_COMPLEX) return -2;
     if (n < 1 || n > SMALL_MAX) return -3;
-    if (threads != 0 && threads != 64 && threads != 128 && threads != 256 && threads != 512) return -4;
+    if (threads != 0 && threads != 64 && threads != 128 && threads != 256 && threads != 512 && threads != 1024)
+        return -4;
     if (threads != 0 && (wg_per_cu < 1 || wg_per_cu > 32)) return -5;
     const int bk = small_bucket(n);
     h->bthreads[dtype][bk] = threads;
@@ -375,8 +378,8 @@ int gevd_tune_batched(gevd_handle h, int dtype, int n, int count, int* threads, 
     const int saved_t = h->bthreads[dtype][bk], saved_w = h->bwgpcu[dtype][bk];
     float best = 3.0e38f;
     int bt = 0, bw = 0, rc = 0;
-    const int cand_t[4] = {64, 128, 256, 512};
-    for (int ti = 0; ti < 4 && !rc; ++ti) {
+    const int cand_t[5] = {64, 128, 256, 512, 1024};
+    for (int ti = 0; ti < 5 && !rc; ++ti) {
         const int t = cand_t[ti];
         const int occ = small_occupancy(cx, t, nb);
         int ws[3] = {1, std::max(1, occ / 2), occ};

@@ -847,6 +847,7 @@ const void* kfun_t(int threads) {
         case 128: return kfun<T, 128>();
         case 256: return kfun<T, 256>();
         case 512: return kfun<T, 512>();
+        case 1024: return kfun<T, 1024>();
         default: return nullptr;
     }
 }
@@ -865,6 +866,7 @@ int go_t(hipStream_t st, int threads, int grid, int nmax, const SmallDesc* desc,
         case 128: go<T, 128>(st, grid, nmax, desc, count, zws, counter); break;
         case 256: go<T, 256>(st, grid, nmax, desc, count, zws, counter); break;
         case 512: go<T, 512>(st, grid, nmax, desc, count, zws, counter); break;
+        case 1024: go<T, 1024>(st, grid, nmax, desc, count, zws, counter); break;
         default: return GEVD_E_STATE;
     }
     GEVD_LAUNCH_CHECK();

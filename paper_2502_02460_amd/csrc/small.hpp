@@ -35,7 +35,7 @@ int small_prepare(bool cx, int threads, int nmax);
 int small_occupancy(bool cx, int threads, int nmax);
 
 // Launch: zero the queue counter, then `grid` persistent workgroups of
-// `threads` (64, 128, 256 or 512) lanes drain `count` problems of one dtype
+// `threads` (64, 128, 256, 512 or 1024) lanes drain `count` problems of one dtype
 // with n <= nmax.  zws holds grid * small_zslot(nmax) doubles.  Nothing here
 // synchronises or allocates, so the sequence may be captured in a graph.
 int small_launch(hipStream_t st, bool cx, int threads, int grid, int nmax, const SmallDesc* desc, int count,

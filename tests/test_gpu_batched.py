@@ -164,7 +164,7 @@ def test_degenerate_spectrum(solver):
 
 def test_tuner_and_shapes(gpu_lib, solver):
     t, w = solver.tune_batched(torch.float64, 60, count=96)
-    assert t in (64, 128, 256, 512) and w >= 1
+    assert t in (64, 128, 256, 512, 1024) and w >= 1
     assert solver.batch_shape(torch.float64, 33) == (t, w)
     p = synth.pencil(60, False, 1e-3, 5, 1.0)
     (wv, C), = solver.solve_batched(_items([p]))[0]
@@ -179,7 +179,7 @@ def test_result_independent_of_launch_shape(solver):
     shape (lanes per workgroup, workgroups per CU) changes speed only."""
     ps = [synth.pencil(n, c, 1e-6, 300 + n, 0.3) for n, c in ((100, False), (300, True), (480, False))]
     outs = []
-    for threads, wg in ((64, 4), (256, 1), (512, 1)):
+    for threads, wg in ((64, 4), (256, 1), (512, 1), (1024, 1)):
         for dt in (torch.float64, torch.complex128):
             for n in (64, 128, 256, 512):
                 solver.set_batch_shape(dt, n, threads, wg)
