@@ -102,6 +102,14 @@ extern "C" int gevd_solve_batched_noalloc(gevd_handle h, int count, const gevd_p
         const int nmax = small_bucket_n(bucket);
         int threads = 0, wg = 1;
         batch_shape_of(h, cx, bucket, &threads, &wg);
+        // the wider workgroup shapes spill registers, and a kernel with spills
+        // needs private scratch that the runtime provides at launch: keep to
+        // shapes that fit in registers (results do not depend on the shape)
+        const int tfit = cx ? 256 : 512;
+        if (threads > tfit) {
+            threads = tfit;
+            wg = std::max(1, small_occupancy(cx, threads, nmax));
+        }
         const long slots = zdoubles / small_zslot(nmax);
         if (slots < 1) {
             rc = GEVD_E_SCRATCH;
